@@ -1,0 +1,191 @@
+"""Benchmark: GDOF/s of the fused FP64 PA diffusion apply on one MI355X, plus the
+Jacobi-PCG time to a 1e-8 relative residual, next to the CPU oracle.
+
+Workload (one step = one operator apply y = K x, the whole fused kernel):
+  48^3 hexahedra of the unit cube, interior vertices perturbed by U[-0.1h, 0.1h],
+  p = 4 (GLL nodes), Q = 6 Gauss points per axis, kappa = 1 + 0.5 sin(2 pi x) sin(2 pi y) sin(2 pi z),
+  x ~ U[-1, 1]: 7,189,057 DOFs.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  `--sweep` adds the p = 2, 4, 6, 8 mass/diffusion sweep (~30 M DOFs each).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def alg_bytes(ndof, nelem, p, q, ops):
+    """Algorithmic HBM bytes of one apply: D (FP64), the int32 DOF map, read x, write y."""
+    ncomp = (6 if ops & 2 else 0) + (1 if ops & 1 else 0)
+    return nelem * ncomp * q ** 3 * 8 + nelem * (p + 1) ** 3 * 4 + 16 * ndof
+
+
+def alg_flops(nelem, p, q, ops):
+    """Sum-factorised FLOPs per element (multiply-add = 2), no MFMA padding:
+    diffusion 2 [2 (2Qd^3 + 3Q^2d^2 + 3Q^3d) + 9Q^3], mass 2 [2 (Qd^3 + Q^2d^2 + Q^3d) + Q^3]."""
+    d = p + 1
+    f = 0
+    if ops & 2:
+        f += 2 * (2 * (2 * q * d ** 3 + 3 * q * q * d * d + 3 * q ** 3 * d) + 9 * q ** 3)
+    if ops & 1:
+        f += 2 * (2 * (q * d ** 3 + q * q * d * d + q ** 3 * d) + q ** 3)
+    return nelem * f
+
+
+def time_kernel(op, hexpa, x, y, steps, warmup):
+    """Average duration of the fused kernel alone (pa_apply_add: one launch), HIP events on
+    the stream the kernel is launched on, and the median of per-apply (fill + kernel) times."""
+    import torch
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        hexpa.pa_apply(op.h, x, y)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(s)
+        hexpa.pa_apply_add(op.h, x, y)
+        b.record(s)
+    torch.cuda.synchronize()
+    kern = [a.elapsed_time(b) for a, b in ev]
+    return float(np.mean(kern)), float(np.median(kern))
+
+
+def cpu_baseline(mesh, p, q, coeff_o, ops_o, ndof, nelem, budget_s):
+    import oracle
+    P = oracle.Problem(mesh, p, q, coeff=coeff_o, ops=ops_o)
+    x = np.random.default_rng(7).uniform(-1, 1, ndof)
+    rng = np.random.default_rng(11)
+    n_try = 16
+    t0 = time.perf_counter()
+    P.apply(x, subset=np.sort(rng.choice(nelem, n_try, replace=False)))
+    t_try = time.perf_counter() - t0
+    n_el = int(min(nelem, max(n_try, n_try * budget_s / max(t_try, 1e-6))))
+    sub = np.sort(rng.choice(nelem, n_el, replace=False))
+    t0 = time.perf_counter()
+    P.apply(x, subset=sub)
+    t = time.perf_counter() - t0
+    dofs_equiv = ndof * n_el / nelem
+    return {"value": dofs_equiv / t / 1e9, "unit": "GDOF/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n_el} of {nelem} elements (random, seed 11), element matrices assembled on the fly "
+                      f"by quadrature loops and applied; {t:.1f} s; throughput scaled by the DOF share"}
+
+
+def run_cg(hexpa, mesh, coeff, p, q):
+    import torch
+    import synth
+    op = hexpa.PAOperator(mesh, p, q, coeff=coeff, ops=hexpa.PA_DIFFUSION, ess_mode=1)
+    xq = op.qpoints().cpu().numpy().reshape(-1, 3)
+    b = op.load(torch.tensor(synth.f_manufactured(xq).reshape(op.nelem, -1), device="cuda"))
+    ess = torch.tensor(hexpa.pa_get_ess(op.h), device="cuda", dtype=torch.long)
+    b[ess] = 0.0
+    torch.cuda.synchronize()
+    x = torch.zeros_like(b)
+    res = hexpa.cg_solve(op.h, b, x, rtol=1e-8, max_it=20000, mode=hexpa.PA_CG_JACOBI, check_every=1,
+                         raise_on_fail=False)
+    u = torch.tensor(synth.u_manufactured(op.nodes().cpu().numpy()), device="cuda")
+    err = float((x - u).abs().max())
+    op.close()
+    return {"mode": "jacobi_pcg_fp64", "rtol": 1e-8, "iters": res["iters"], "seconds": res["seconds"],
+            "rel_res_true": res["rel_res_true"], "status": res["rc"], "max_nodal_error_vs_exact_u": err}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--variant", default="mfma", choices=["mfma", "valu", "colored"])
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0 = skip)")
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--sweep", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2603_09038_amd import hexpa
+    torch.cuda.set_device(0)
+
+    n, p, q = 48, 4, 6
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    coeff = {"kind": hexpa.PA_COEFF_SINE, "value": 1.0, "amp": 0.5, "freq": 2.0}
+    op = hexpa.PAOperator(mesh, p, q, coeff=coeff, ops=hexpa.PA_DIFFUSION)
+    op.set_variant({"mfma": hexpa.PA_VARIANT_MFMA, "valu": hexpa.PA_VARIANT_VALU,
+                    "colored": hexpa.PA_VARIANT_MFMA_COLORED}[args.variant])
+    ndof, nelem = op.ndof, op.nelem
+    x = torch.tensor(synth.rand_x(ndof, 0), device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` full applies (fill + fused kernel)
+    for _ in range(args.warmup):
+        hexpa.pa_apply(op.h, x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hexpa.pa_apply(op.h, x, y)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    gdofs = ndof / (wall / args.steps) / 1e9
+
+    k_mean_ms, k_med_ms = time_kernel(op, hexpa, x, y, args.steps, 3)
+    ab = alg_bytes(ndof, nelem, p, q, 2)
+    achieved = ab / (k_mean_ms * 1e-3) / 1e9
+    out = {
+        "metric": "GDOF/s PA diffusion apply p=2..8; CG time-to-1e-8 mixed/learned vs FP64",
+        "value": gdofs, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "fp64 PA diffusion apply, 48^3 perturbed hex mesh, p=4, Q=6, "
+                               "kappa=1+0.5sin(2pi x)sin(2pi y)sin(2pi z), x~U[-1,1]",
+                   "ndof": ndof, "nelem": nelem, "p": p, "q1d": q, "variant": args.variant},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_apply<5,6,2,mfma>", "alg_bytes_per_launch": ab,
+                     "alg_bytes_per_dof": ab / ndof, "kernel_ms_mean": k_mean_ms, "kernel_ms_median": k_med_ms,
+                     "kernel_gdofs": ndof / (k_mean_ms * 1e-3) / 1e9,
+                     "fp64_frac": alg_flops(nelem, p, q, 2) / (k_mean_ms * 1e-3) / 78.6e12},
+    }
+    if not args.no_cg:
+        out["cg"] = run_cg(hexpa, mesh, coeff, p, q)
+    op.close()
+    if args.sweep:
+        sweep = []
+        for pp, nn in ((2, 155), (4, 78), (6, 52), (8, 40)):
+            m2 = synth.box_mesh(nn, perturb=0.1, seed=0)
+            for ops in (hexpa.PA_MASS, hexpa.PA_DIFFUSION):
+                o2 = hexpa.PAOperator(m2, pp, pp + 2, ops=ops)
+                o2.set_variant({"mfma": 0, "valu": 1, "colored": 2}[args.variant])
+                x2 = torch.tensor(synth.rand_x(o2.ndof, 0), device="cuda")
+                y2 = torch.empty_like(x2)
+                km, _ = time_kernel(o2, hexpa, x2, y2, 20, 5)
+                ab2 = alg_bytes(o2.ndof, o2.nelem, pp, pp + 2, ops)
+                sweep.append({"p": pp, "n": nn, "op": "mass" if ops == 1 else "diffusion", "ndof": o2.ndof,
+                              "kernel_ms": km, "gdofs": o2.ndof / (km * 1e-3) / 1e9,
+                              "hbm_frac": ab2 / (km * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                o2.close()
+                del x2, y2
+                torch.cuda.empty_cache()
+        out["sweep"] = sweep
+    if args.cpu_budget > 0:
+        import oracle
+        out["cpu_baseline"] = cpu_baseline(mesh, p, q, oracle.Coeff.sine(), oracle.DIFFUSION, ndof, nelem,
+                                           args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,181 @@
+/*
+ * hexpa — partial-assembly (PA) action of high-order H1 mass and diffusion operators
+ * on hexahedral meshes, and the CG solves that run on it, for AMD Instinct MI355X (gfx950).
+ *
+ * The operator is the decomposition A = P^T G^T B^T D B G P of the paper's eq. (1)
+ * (Sec. II-B): G maps the global (L-)vector to element (E-)vectors through a DOF map,
+ * B evaluates the tensor-product basis at quadrature points by sum factorization
+ * (eq. (2)), and D is the block-diagonal quadrature-point data that partial assembly
+ * precomputes and stores.  On one device P = I.
+ *
+ * Conventions shared by every call
+ *  - reference element [0,1]^3; local node I = i + d*j + d*d*k with d = p+1 (i fastest);
+ *    nodes are Gauss-Lobatto-Legendre points; quadrature is q1d-point Gauss-Legendre per axis;
+ *  - hex corner c = a + 2b + 4c' sits at reference vertex (a, b, c') (lexicographic);
+ *  - quadrature point r = a + q1d*(b + q1d*c) (a fastest);
+ *  - all vector arguments of pa_apply/pa_diag/pa_load/cg_solve are DEVICE pointers owned
+ *    by the caller (e.g. torch tensors), FP64, length ndof unless stated;
+ *    mesh/coefficient descriptors point to HOST memory, copied during pa_setup
+ *    (the caller may free them afterwards);
+ *  - `stream` is a hipStream_t (NULL = legacy default stream); calls marked
+ *    "asynchronous" only enqueue work on it;
+ *  - every int-returning call returns PA_OK (0) or a negative status; the message of the
+ *    last failure on the calling thread is available from pa_last_error().  No C++
+ *    exception crosses this interface.  Null pointers, sizes that do not match the
+ *    operator, and unsupported (p, q1d) pairs are rejected before any launch.
+ */
+#ifndef HEXPA_H
+#define HEXPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define PA_OK 0
+#define PA_ERR_ARG (-1)           /* bad pointer, size or option */
+#define PA_ERR_HIP (-2)           /* a HIP runtime call failed */
+#define PA_ERR_UNSUPPORTED (-3)   /* (p, q1d, ops) combination not compiled in */
+#define PA_ERR_MESH (-4)          /* an element has det J <= 0 at a quadrature point */
+#define PA_ERR_NOT_CONVERGED (-5) /* solver hit max_it before the tolerance */
+#define PA_ERR_BREAKDOWN (-6)     /* solver breakdown: p^T A p <= 0 or a non-finite scalar */
+#define PA_ERR_IO (-7)            /* file read/write/format error */
+
+/* ------------------------------------------------------------------ operator bits */
+#define PA_MASS 1u      /* (kappa u, v)               D = w kappa det J            (1 value / qp) */
+#define PA_DIFFUSION 2u /* (kappa grad u, grad v)     D = w kappa adj(J) adj(J)^T / det J
+                           (symmetric 3x3, 6 values / qp, order 00,01,02,11,12,22) */
+
+/* ------------------------------------------------------------------ descriptors */
+typedef struct {
+    int32_t nvert;
+    const double *vert_xyz; /* host [nvert][3] vertex coordinates */
+    int32_t nelem;
+    const int32_t *hex;     /* host [nelem][8] vertex indices, corner c = a + 2b + 4c' */
+    /* Structured box: nx = ny = nz = n > 0 means elements are ordered e = ex + n*(ey + n*ez)
+       and the library numbers DOFs on the (n p + 1)^3 lattice: node (ex p + i, ey p + j, ez p + k)
+       gets index I + M*(J + M*K), M = n p + 1.  Otherwise (0,0,0) and elem_dofs is required. */
+    int32_t nx, ny, nz;
+    const int32_t *elem_dofs; /* optional host [nelem][(p+1)^3] DOF map (used when nx == 0) */
+    int32_t ndof;             /* number of DOFs when elem_dofs is given; ignored for boxes */
+    /* Essential (Dirichlet) DOFs: ess_mode 0 = none, 1 = all DOFs on the box boundary
+       (structured boxes only), 2 = ess_marker[ndof] (host, nonzero = essential). */
+    int32_t ess_mode;
+    const uint8_t *ess_marker;
+} pa_mesh_desc;
+
+#define PA_COEFF_CONST 0 /* kappa = value */
+#define PA_COEFF_SINE 1  /* kappa = value + amp sin(freq pi x) sin(freq pi y) sin(freq pi z) */
+#define PA_COEFF_GRID 2  /* kappa = trilinear interpolation of grid[gz][gy][gx] (x fastest)
+                            on [0,1]^3, clamped to the cube */
+typedef struct {
+    int32_t kind;
+    double value, amp, freq;
+    const double *grid; /* host */
+    int32_t gx, gy, gz;
+} pa_coeff_desc;
+
+/* Apply-kernel variants (pa_set_variant). */
+#define PA_VARIANT_MFMA 0    /* fused kernel, FP64 MFMA contractions, atomic scatter (default) */
+#define PA_VARIANT_VALU 1    /* fused kernel, FP64 vector-ALU contractions, atomic scatter */
+#define PA_VARIANT_MFMA_COLORED 2 /* MFMA contractions, 8 colour launches, plain read-modify-write
+                                     scatter: bitwise reproducible */
+
+typedef struct pa_op pa_op;
+
+typedef struct {
+    int32_t p, q1d, ops, nelem, ndof, ness, ncomp, variant, elems_per_block;
+    int64_t qdata_bytes; /* bytes of stored quadrature-point data D */
+    int64_t map_bytes;   /* bytes of the DOF map G */
+} pa_info_t;
+
+/* ------------------------------------------------------------------ operator calls */
+
+/* Build the PA operator (paper Sec. II-B: "precompute and store ... D at quadrature
+   points").  Copies the mesh to the device, builds the DOF map G, the 1-D basis tables
+   (values B and derivatives at the q1d Gauss points) and computes D in FP64 on the
+   device.  order p in [1,8], q1d in {p+1, p+2}; ops = PA_MASS, PA_DIFFUSION or both
+   (A = M + K).  Synchronous.  On success *out owns all device memory it allocated. */
+int pa_setup(const pa_mesh_desc *mesh, int order, int q1d, const pa_coeff_desc *coeff,
+             uint32_t ops, void *stream, pa_op **out);
+
+/* y = A x (eq. (1) with P = I: gather G, contractions B, D at quadrature points,
+   transposed contractions B^T, scatter-add G^T), one fused kernel.  y is overwritten.
+   x and y must not alias.  Asynchronous. */
+int pa_apply(pa_op *op, const double *x, double *y, void *stream);
+
+/* y += A x: the same fused kernel without zeroing y first (one kernel launch; used to
+   accumulate several operators into one vector and to time the kernel alone).
+   x and y must not alias.  Asynchronous. */
+int pa_apply_add(pa_op *op, const double *x, double *y, void *stream);
+
+/* y = A_c x with A_c = (I - E) A (I - E) + E, E = indicator of the essential DOFs.
+   Uses handle-owned scratch; calls on one handle must not overlap.  Asynchronous. */
+int pa_apply_constrained(pa_op *op, const double *x, double *y, void *stream);
+
+/* d = diag(A) (constrained = 0) or diag(A_c) (constrained != 0: 1 on essential rows),
+   computed by sum factorization over the stored D.  Asynchronous. */
+int pa_diag(pa_op *op, double *d, int constrained, void *stream);
+
+/* Load vector b = G^T B^T (w det J f): f given at quadrature points, device
+   [nelem][q1d^3] in the quadrature-point order above; b overwritten.  Asynchronous. */
+int pa_load(pa_op *op, const double *f_qp, double *b, void *stream);
+
+/* Physical coordinates of the quadrature points, device out [nelem][q1d^3][3]. Asynchronous. */
+int pa_qpoints(pa_op *op, double *xyz, void *stream);
+
+/* Physical coordinates of the DOF nodes, device out [ndof][3].  Asynchronous. */
+int pa_nodes(pa_op *op, double *xyz, void *stream);
+
+/* Copy the DOF map G to host memory [nelem][(p+1)^3].  Synchronous. */
+int pa_get_elem_dofs(pa_op *op, int32_t *host_out);
+
+/* Copy the essential-DOF list to host memory [ness] (ascending).  Synchronous. */
+int pa_get_ess(pa_op *op, int32_t *host_out);
+
+/* Select the apply kernel (PA_VARIANT_*).  Takes effect for later calls. */
+int pa_set_variant(pa_op *op, int variant);
+
+int pa_info(const pa_op *op, pa_info_t *info);
+void pa_destroy(pa_op *op);
+const char *pa_last_error(void);
+
+/* ------------------------------------------------------------------ solver */
+#define PA_CG_PLAIN 0      /* CG, no preconditioner */
+#define PA_CG_JACOBI 1     /* Jacobi-preconditioned CG, M = diag(A_c) */
+
+typedef struct {
+    double rtol;         /* stop when ||r_k||_2 <= rtol ||b||_2 (recursive residual) */
+    int32_t max_it;
+    int32_t mode;        /* PA_CG_* */
+    int32_t check_every; /* read the residual norm back to the host every k iterations (>=1) */
+    int32_t constrained; /* 1: solve with A_c (b must vanish on essential DOFs) */
+} pa_cg_opts;
+
+typedef struct {
+    int32_t iters, status;
+    double rel_res_recursive; /* ||r_k|| / ||b|| of the recursion at exit */
+    double rel_res_true;      /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
+    double seconds;           /* wall time of the iteration (excludes diag and setup) */
+} pa_cg_result;
+
+/* Solve A x = b (or A_c x = b) by (preconditioned) CG (Saad, Alg. 9.1), all vector work
+   and reductions in FP64 on the device.  x is the initial guess on entry and the
+   solution on exit.  Synchronous on `stream`.  Returns PA_OK, PA_ERR_NOT_CONVERGED
+   (x holds the last iterate) or PA_ERR_BREAKDOWN. */
+int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
+             pa_cg_result *res, void *stream);
+
+/* ------------------------------------------------------------------ diagnostics */
+
+/* One v_mfma_f64_16x16x4f64 on the device: D[16][16] = A[16][4] * B[4][16] (row-major,
+   device pointers).  Used by the tests to pin the operand/lane layout the kernels assume. */
+int pa_debug_mfma_f64(const double *A, const double *B, double *D, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEXPA_H */

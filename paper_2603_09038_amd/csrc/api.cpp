@@ -1,0 +1,542 @@
+// C-ABI of the hexpa library: operator setup/apply/diag/load, Jacobi-PCG, diagnostics.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "k_vec.h"
+
+namespace hexpa {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+hipError_t launch_apply_p1(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+hipError_t launch_apply_p2(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+hipError_t launch_apply_p3(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+hipError_t launch_apply_p4(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+hipError_t launch_apply_p5(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+hipError_t launch_apply_p6(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+hipError_t launch_apply_p7(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+hipError_t launch_apply_p8(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+
+hipError_t launch_apply(const pa_op *op, int variant, const double *x, double *y, const int32_t *elist, int n,
+                        hipStream_t s, bool *ok)
+{
+    switch (op->p) {
+    case 1: return launch_apply_p1(op, variant, x, y, elist, n, s, ok);
+    case 2: return launch_apply_p2(op, variant, x, y, elist, n, s, ok);
+    case 3: return launch_apply_p3(op, variant, x, y, elist, n, s, ok);
+    case 4: return launch_apply_p4(op, variant, x, y, elist, n, s, ok);
+    case 5: return launch_apply_p5(op, variant, x, y, elist, n, s, ok);
+    case 6: return launch_apply_p6(op, variant, x, y, elist, n, s, ok);
+    case 7: return launch_apply_p7(op, variant, x, y, elist, n, s, ok);
+    case 8: return launch_apply_p8(op, variant, x, y, elist, n, s, ok);
+    }
+    *ok = false;
+    return hipSuccess;
+}
+
+}  // namespace hexpa
+
+using namespace hexpa;
+
+#define PA_TRY try {
+#define PA_CATCH                                                  \
+    }                                                             \
+    catch (const std::bad_alloc &) {                              \
+        set_error("host allocation failed");                      \
+        return PA_ERR_ARG;                                        \
+    }                                                             \
+    catch (...) {                                                 \
+        set_error("unexpected host exception");                   \
+        return PA_ERR_ARG;                                        \
+    }
+
+#define HIP_OK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            set_error(std::string(#expr) + " failed: " + hipGetErrorString(_e));       \
+            return PA_ERR_HIP;                                                         \
+        }                                                                              \
+    } while (0)
+
+static int arg_error(const char *msg)
+{
+    set_error(msg);
+    return PA_ERR_ARG;
+}
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+static void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+template <class T>
+static hipError_t dalloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, n * sizeof(T) + 16);
+}
+
+extern "C" const char *pa_last_error(void) { return g_err.c_str(); }
+
+extern "C" void pa_destroy(pa_op *op)
+{
+    if (!op) return;
+    dfree(op->d_elem_dofs);
+    dfree(op->d_qdata);
+    dfree(op->d_vert);
+    dfree(op->d_hex);
+    dfree(op->d_tab);
+    dfree(op->d_grid);
+    dfree(op->d_ess);
+    dfree(op->d_color_elems);
+    dfree(op->d_scratch);
+    delete op;
+}
+
+extern "C" int pa_setup(const pa_mesh_desc *m, int order, int q1d, const pa_coeff_desc *c, uint32_t ops,
+                        void *stream, pa_op **out)
+{
+    PA_TRY
+    if (!out) return arg_error("pa_setup: out is NULL");
+    *out = nullptr;
+    if (!m || !m->vert_xyz || !m->hex || m->nvert <= 0 || m->nelem <= 0)
+        return arg_error("pa_setup: mesh descriptor incomplete");
+    if (order < 1 || order > kMaxP) {
+        set_error("pa_setup: order must be in [1, 8]");
+        return PA_ERR_UNSUPPORTED;
+    }
+    if (q1d != order + 1 && q1d != order + 2) {
+        set_error("pa_setup: q1d must be order+1 or order+2");
+        return PA_ERR_UNSUPPORTED;
+    }
+    if (ops < 1 || ops > 3) return arg_error("pa_setup: ops must be PA_MASS, PA_DIFFUSION or both");
+    if (c && c->kind == PA_COEFF_GRID && (!c->grid || c->gx < 2 || c->gy < 2 || c->gz < 2))
+        return arg_error("pa_setup: grid coefficient needs grid and gx, gy, gz >= 2");
+    if (c && (c->kind < PA_COEFF_CONST || c->kind > PA_COEFF_GRID)) return arg_error("pa_setup: unknown coefficient kind");
+    hipStream_t s = as_stream(stream);
+
+    std::unique_ptr<pa_op, void (*)(pa_op *)> op(new pa_op, pa_destroy);
+    op->p = order; op->d = order + 1; op->q = q1d; op->ops = (int)ops;
+    op->ncomp = (ops & PA_DIFFUSION) ? ((ops & PA_MASS) ? 7 : 6) : 1;
+    op->nelem = m->nelem; op->nvert = m->nvert;
+    std::string terr;
+    if (!make_tables(order, q1d, op->tab, terr)) return arg_error(terr.c_str());
+
+    const int d = op->d, d3 = d * d * d;
+    const int64_t nel = m->nelem;
+    std::vector<int32_t> ed((size_t)nel * d3);
+    std::vector<uint8_t> marker;
+    if (m->nx > 0) {
+        const int64_t nx = m->nx, ny = m->ny, nz = m->nz;
+        if (ny <= 0 || nz <= 0 || nx * ny * nz != nel) return arg_error("pa_setup: nx*ny*nz != nelem");
+        const int64_t Mx = nx * order + 1, My = ny * order + 1, Mz = nz * order + 1;
+        if (Mx * My * Mz > INT32_MAX) return arg_error("pa_setup: too many DOFs for int32 indices");
+        op->nx = (int)nx; op->ny = (int)ny; op->nz = (int)nz;
+        op->ndof = (int)(Mx * My * Mz);
+        for (int64_t e = 0; e < nel; ++e) {
+            const int64_t ex = e % nx, ey = (e / nx) % ny, ez = e / (nx * ny);
+            int32_t *dst = &ed[(size_t)e * d3];
+            for (int k = 0; k < d; ++k)
+                for (int j = 0; j < d; ++j)
+                    for (int i = 0; i < d; ++i)
+                        dst[i + d * (j + d * k)] =
+                            (int32_t)((ex * order + i) + Mx * ((ey * order + j) + My * (ez * order + k)));
+        }
+        if (m->ess_mode == 1) {
+            marker.assign((size_t)op->ndof, 0);
+            for (int64_t K = 0; K < Mz; ++K)
+                for (int64_t J = 0; J < My; ++J)
+                    for (int64_t I = 0; I < Mx; ++I)
+                        if (I == 0 || J == 0 || K == 0 || I == Mx - 1 || J == My - 1 || K == Mz - 1)
+                            marker[(size_t)(I + Mx * (J + My * K))] = 1;
+        }
+    } else {
+        if (!m->elem_dofs || m->ndof <= 0) return arg_error("pa_setup: unstructured mesh needs elem_dofs and ndof");
+        op->ndof = m->ndof;
+        std::memcpy(ed.data(), m->elem_dofs, ed.size() * sizeof(int32_t));
+        for (int32_t v : ed)
+            if (v < 0 || v >= m->ndof) return arg_error("pa_setup: elem_dofs entry out of [0, ndof)");
+        if (m->ess_mode == 1) return arg_error("pa_setup: ess_mode 1 needs a structured box");
+    }
+    if (m->ess_mode == 2) {
+        if (!m->ess_marker) return arg_error("pa_setup: ess_mode 2 needs ess_marker");
+        marker.assign(m->ess_marker, m->ess_marker + op->ndof);
+    } else if (m->ess_mode != 0 && m->ess_mode != 1) {
+        return arg_error("pa_setup: unknown ess_mode");
+    }
+    std::vector<int32_t> ess;
+    for (size_t i = 0; i < marker.size(); ++i)
+        if (marker[i]) ess.push_back((int32_t)i);
+    op->ness = (int)ess.size();
+    for (int32_t h : std::vector<int32_t>(m->hex, m->hex + 8 * nel))
+        if (h < 0 || h >= m->nvert) return arg_error("pa_setup: hex vertex index out of range");
+
+    // colour classes (structured boxes): colour = parity of (ex, ey, ez)
+    std::vector<int32_t> colors;
+    if (op->nx > 0) {
+        std::vector<std::vector<int32_t>> cl(8);
+        for (int64_t e = 0; e < nel; ++e) {
+            const int64_t ex = e % op->nx, ey = (e / op->nx) % op->ny, ez = e / ((int64_t)op->nx * op->ny);
+            cl[(ex & 1) + 2 * (ey & 1) + 4 * (ez & 1)].push_back((int32_t)e);
+        }
+        op->color_off[0] = 0;
+        for (int k = 0; k < 8; ++k) {
+            colors.insert(colors.end(), cl[k].begin(), cl[k].end());
+            op->color_off[k + 1] = (int)colors.size();
+        }
+    }
+
+    DevTables ht;
+    std::memset(&ht, 0, sizeof(ht));
+    for (int a = 0; a < q1d; ++a) {
+        ht.w[a] = op->tab.qwts[a];
+        ht.x[a] = op->tab.qpts[a];
+        for (int i = 0; i < d; ++i) {
+            ht.B[a * d + i] = op->tab.B[(size_t)a * d + i];
+            ht.G[a * d + i] = op->tab.G[(size_t)a * d + i];
+        }
+    }
+    for (int i = 0; i < d; ++i) ht.nodes[i] = op->tab.nodes[i];
+
+    const int q3 = q1d * q1d * q1d;
+    HIP_OK(hipGetDevice(&op->device));
+    HIP_OK(dalloc(&op->d_elem_dofs, ed.size()));
+    HIP_OK(dalloc(&op->d_qdata, (size_t)nel * op->ncomp * q3));
+    HIP_OK(dalloc(&op->d_vert, (size_t)m->nvert * 3));
+    HIP_OK(dalloc(&op->d_hex, (size_t)nel * 8));
+    HIP_OK(dalloc(&op->d_tab, 1));
+    HIP_OK(dalloc(&op->d_scratch, (size_t)op->ndof));
+    op->scratch_len = (size_t)op->ndof;
+    HIP_OK(hipMemcpy(op->d_elem_dofs, ed.data(), ed.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(op->d_vert, m->vert_xyz, (size_t)m->nvert * 3 * sizeof(double), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(op->d_hex, m->hex, (size_t)nel * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(op->d_tab, &ht, sizeof(ht), hipMemcpyHostToDevice));
+    if (!ess.empty()) {
+        HIP_OK(dalloc(&op->d_ess, ess.size()));
+        HIP_OK(hipMemcpy(op->d_ess, ess.data(), ess.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    if (!colors.empty()) {
+        HIP_OK(dalloc(&op->d_color_elems, colors.size()));
+        HIP_OK(hipMemcpy(op->d_color_elems, colors.data(), colors.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    CoeffDev cf{PA_COEFF_CONST, 1.0, 0.0, 0.0, nullptr, 0, 0, 0};
+    if (c) {
+        cf.kind = c->kind; cf.value = c->value; cf.amp = c->amp; cf.freq = c->freq;
+        if (c->kind == PA_COEFF_GRID) {
+            const size_t ng = (size_t)c->gx * c->gy * c->gz;
+            HIP_OK(dalloc(&op->d_grid, ng));
+            HIP_OK(hipMemcpy(op->d_grid, c->grid, ng * sizeof(double), hipMemcpyHostToDevice));
+            cf.grid = op->d_grid; cf.gx = c->gx; cf.gy = c->gy; cf.gz = c->gz;
+        }
+    }
+    int *d_bad = nullptr;
+    HIP_OK(hipMalloc((void **)&d_bad, sizeof(int)));
+    HIP_OK(hipMemsetAsync(d_bad, 0, sizeof(int), s));
+    HIP_OK(launch_setup_qdata(op.get(), cf, d_bad, s));
+    int bad = 0;
+    HIP_OK(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    dfree(d_bad);
+    if (bad) {
+        set_error("pa_setup: an element has det J <= 0 at a quadrature point");
+        return PA_ERR_MESH;
+    }
+    *out = op.release();
+    return PA_OK;
+    PA_CATCH
+}
+
+static int do_apply(pa_op *op, int variant, const double *x, double *y, hipStream_t s, bool zero_first = true)
+{
+    bool ok = true;
+    if (zero_first) HIP_OK(vec_fill(y, 0.0, op->ndof, s));
+    if (variant == PA_VARIANT_MFMA_COLORED) {
+        if (!op->d_color_elems) {
+            set_error("coloured apply needs a structured box mesh");
+            return PA_ERR_UNSUPPORTED;
+        }
+        for (int c = 0; c < 8 && ok; ++c) {
+            const int n = op->color_off[c + 1] - op->color_off[c];
+            HIP_OK(launch_apply(op, variant, x, y, op->d_color_elems + op->color_off[c], n, s, &ok));
+        }
+    } else {
+        HIP_OK(launch_apply(op, variant, x, y, nullptr, op->nelem, s, &ok));
+    }
+    if (!ok) {
+        set_error("apply kernel not instantiated for this (p, q1d, ops)");
+        return PA_ERR_UNSUPPORTED;
+    }
+    return PA_OK;
+}
+
+extern "C" int pa_apply(pa_op *op, const double *x, double *y, void *stream)
+{
+    PA_TRY
+    if (!op || !x || !y) return arg_error("pa_apply: NULL argument");
+    if (x == y) return arg_error("pa_apply: x and y must not alias");
+    return do_apply(op, op->variant, x, y, as_stream(stream));
+    PA_CATCH
+}
+
+extern "C" int pa_apply_add(pa_op *op, const double *x, double *y, void *stream)
+{
+    PA_TRY
+    if (!op || !x || !y) return arg_error("pa_apply_add: NULL argument");
+    if (x == y) return arg_error("pa_apply_add: x and y must not alias");
+    return do_apply(op, op->variant, x, y, as_stream(stream), false);
+    PA_CATCH
+}
+
+// y = A_c x; uses op->d_scratch for the masked input.
+static int do_apply_constrained(pa_op *op, const double *x, double *y, hipStream_t s)
+{
+    if (op->ness == 0) return do_apply(op, op->variant, x, y, s);
+    HIP_OK(vec_copy(op->d_scratch, x, op->ndof, s));
+    HIP_OK(vec_zero_list(op->d_scratch, op->d_ess, op->ness, s));
+    int rc = do_apply(op, op->variant, op->d_scratch, y, s);
+    if (rc) return rc;
+    HIP_OK(vec_copy_list(y, x, op->d_ess, op->ness, s));
+    return PA_OK;
+}
+
+extern "C" int pa_apply_constrained(pa_op *op, const double *x, double *y, void *stream)
+{
+    PA_TRY
+    if (!op || !x || !y) return arg_error("pa_apply_constrained: NULL argument");
+    if (x == y) return arg_error("pa_apply_constrained: x and y must not alias");
+    return do_apply_constrained(op, x, y, as_stream(stream));
+    PA_CATCH
+}
+
+extern "C" int pa_diag(pa_op *op, double *dg, int constrained, void *stream)
+{
+    PA_TRY
+    if (!op || !dg) return arg_error("pa_diag: NULL argument");
+    hipStream_t s = as_stream(stream);
+    HIP_OK(launch_diag(op, dg, s));
+    if (constrained && op->ness) HIP_OK(vec_set_list(dg, 1.0, op->d_ess, op->ness, s));
+    return PA_OK;
+    PA_CATCH
+}
+
+extern "C" int pa_load(pa_op *op, const double *f_qp, double *b, void *stream)
+{
+    PA_TRY
+    if (!op || !f_qp || !b) return arg_error("pa_load: NULL argument");
+    HIP_OK(launch_load(op, f_qp, b, as_stream(stream)));
+    return PA_OK;
+    PA_CATCH
+}
+
+extern "C" int pa_qpoints(pa_op *op, double *xyz, void *stream)
+{
+    PA_TRY
+    if (!op || !xyz) return arg_error("pa_qpoints: NULL argument");
+    HIP_OK(launch_qpoints(op, xyz, as_stream(stream)));
+    return PA_OK;
+    PA_CATCH
+}
+
+extern "C" int pa_nodes(pa_op *op, double *xyz, void *stream)
+{
+    PA_TRY
+    if (!op || !xyz) return arg_error("pa_nodes: NULL argument");
+    HIP_OK(launch_nodes(op, xyz, as_stream(stream)));
+    return PA_OK;
+    PA_CATCH
+}
+
+extern "C" int pa_get_elem_dofs(pa_op *op, int32_t *host_out)
+{
+    PA_TRY
+    if (!op || !host_out) return arg_error("pa_get_elem_dofs: NULL argument");
+    HIP_OK(hipMemcpy(host_out, op->d_elem_dofs, (size_t)op->nelem * op->d * op->d * op->d * sizeof(int32_t),
+                     hipMemcpyDeviceToHost));
+    return PA_OK;
+    PA_CATCH
+}
+
+extern "C" int pa_get_ess(pa_op *op, int32_t *host_out)
+{
+    PA_TRY
+    if (!op || (!host_out && op->ness)) return arg_error("pa_get_ess: NULL argument");
+    if (op->ness) HIP_OK(hipMemcpy(host_out, op->d_ess, (size_t)op->ness * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return PA_OK;
+    PA_CATCH
+}
+
+extern "C" int pa_set_variant(pa_op *op, int variant)
+{
+    if (!op) return arg_error("pa_set_variant: NULL op");
+    if (variant < PA_VARIANT_MFMA || variant > PA_VARIANT_MFMA_COLORED) return arg_error("pa_set_variant: unknown variant");
+    if (variant == PA_VARIANT_MFMA_COLORED && !op->d_color_elems) {
+        set_error("pa_set_variant: coloured apply needs a structured box mesh");
+        return PA_ERR_UNSUPPORTED;
+    }
+    op->variant = variant;
+    return PA_OK;
+}
+
+extern "C" int pa_info(const pa_op *op, pa_info_t *info)
+{
+    if (!op || !info) return arg_error("pa_info: NULL argument");
+    info->p = op->p; info->q1d = op->q; info->ops = op->ops; info->nelem = op->nelem; info->ndof = op->ndof;
+    info->ness = op->ness; info->ncomp = op->ncomp; info->variant = op->variant;
+    const int d = op->d, q = op->q;
+    const int ncomp = op->ncomp;
+    // elements per workgroup of the fused kernel (mirrors Shape<>::E)
+    const bool diff = op->ops & PA_DIFFUSION, mass = op->ops & PA_MASS;
+    const int ng = diff ? (mass ? 4 : 3) : 1;
+    auto mx = [](int a, int b) { return a > b ? a : b; };
+    const int sa = mx(d * d * d, mx((diff ? 3 * q * q : q * q) * d, ng * q * q * d)) | 1;
+    const int sb = mx((diff ? 2 * q : q) * d * d, mx(ng * q * q * q, (diff ? 2 : 1) * d * d * q)) | 1;
+    int e = (48 * 1024) / (8 * (sa + sb) + 4 * d * d * d);
+    info->elems_per_block = e < 1 ? 1 : (e > 32 ? 32 : e);
+    info->qdata_bytes = (int64_t)op->nelem * ncomp * q * q * q * 8;
+    info->map_bytes = (int64_t)op->nelem * d * d * d * 4;
+    return PA_OK;
+}
+
+extern "C" int pa_debug_mfma_f64(const double *A, const double *B, double *D, void *stream)
+{
+    if (!A || !B || !D) return arg_error("pa_debug_mfma_f64: NULL argument");
+    HIP_OK(launch_debug_mfma(A, B, D, as_stream(stream)));
+    return PA_OK;
+}
+
+// ------------------------------------------------------------------ CG
+namespace {
+struct CgWork {
+    double *r = nullptr, *p = nullptr, *Ap = nullptr, *dinv = nullptr, *partial = nullptr, *hist = nullptr,
+           *tmp = nullptr;
+    CgScalars *sc = nullptr;
+    double *h_hist = nullptr;  // pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~CgWork()
+    {
+        dfree(r); dfree(p); dfree(Ap); dfree(dinv); dfree(partial); dfree(hist); dfree(tmp);
+        dfree(sc);
+        if (h_hist) (void)hipHostFree(h_hist);
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace
+
+// y = A p with p vanishing on the essential DOFs (CG invariant): A_c p = A p outside, 0 on them.
+static int cg_apply(pa_op *op, bool constrained, const double *p, double *y, hipStream_t s)
+{
+    int rc = do_apply(op, op->variant, p, y, s);
+    if (rc) return rc;
+    if (constrained && op->ness) HIP_OK(vec_zero_list(y, op->d_ess, op->ness, s));
+    return PA_OK;
+}
+
+extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res, void *stream)
+{
+    PA_TRY
+    if (!op || !b || !x || !o || !res) return arg_error("cg_solve: NULL argument");
+    if (!(o->rtol > 0.0) || o->max_it < 1) return arg_error("cg_solve: need rtol > 0 and max_it >= 1");
+    if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI) return arg_error("cg_solve: unknown mode");
+    std::memset(res, 0, sizeof(*res));
+    hipStream_t s = as_stream(stream);
+    const int64_t n = op->ndof;
+    const bool con = o->constrained != 0;
+    const int check = o->check_every < 1 ? 1 : o->check_every;
+    CgWork w;
+    HIP_OK(dalloc(&w.r, n));
+    HIP_OK(dalloc(&w.p, n));
+    HIP_OK(dalloc(&w.Ap, n));
+    HIP_OK(dalloc(&w.partial, 2 * kRedBlocks));
+    HIP_OK(dalloc(&w.hist, 2 * ((size_t)o->max_it + 2)));
+    HIP_OK(dalloc(&w.tmp, 4));
+    HIP_OK(dalloc(&w.sc, 1));
+    HIP_OK(hipHostMalloc((void **)&w.h_hist, 4 * sizeof(double), hipHostMallocDefault));
+    HIP_OK(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&w.ev[1], hipEventDisableTiming));
+    if (o->mode == PA_CG_JACOBI) {
+        HIP_OK(dalloc(&w.dinv, n));
+        int rc = pa_diag(op, w.dinv, con ? 1 : 0, s);
+        if (rc) return rc;
+        HIP_OK(vec_recip(w.dinv, w.dinv, n, s));
+    }
+    if (con && op->ness) HIP_OK(vec_copy_list(x, b, op->d_ess, op->ness, s));
+    // ||b||
+    HIP_OK(vec_dot(b, b, n, w.partial, w.tmp, s));
+    double bb = 0.0;
+    HIP_OK(hipMemcpyAsync(&bb, w.tmp, sizeof(double), hipMemcpyDeviceToHost, s));
+    // r = b - A x, p = M^{-1} r
+    int rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);
+    if (rc) return rc;
+    HIP_OK(cg_init(b, w.r, w.p, w.dinv, n, w.partial, w.sc, w.hist, s));
+    HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(bb);
+    if (bnorm == 0.0) {
+        HIP_OK(vec_fill(x, 0.0, n, s));
+        HIP_OK(hipStreamSynchronize(s));
+        res->status = PA_OK;
+        return PA_OK;
+    }
+    const double tol2 = (o->rtol * bnorm) * (o->rtol * bnorm);
+    double rr = w.h_hist[0];
+    int it = 0, status = PA_ERR_NOT_CONVERGED;
+    auto t0 = std::chrono::steady_clock::now();
+    if (rr <= tol2) status = PA_OK;
+    int pending = -1;  // slot of the residual copy in flight (-1: none)
+    int nchecks = 0;
+    while (status == PA_ERR_NOT_CONVERGED && it < o->max_it) {
+        ++it;
+        rc = cg_apply(op, con, w.p, w.Ap, s);
+        if (rc) return rc;
+        HIP_OK(cg_alpha(w.p, w.Ap, n, w.partial, w.sc, s));
+        HIP_OK(cg_update(x, w.r, w.p, w.Ap, w.dinv, n, w.partial, w.sc, w.hist, it, s));
+        if (it % check == 0 || it == o->max_it) {
+            // lagged check: the host inspects the previous check's copy while this
+            // iteration is already queued, so the device never waits for the host
+            const int slot = (nchecks++) & 1;
+            HIP_OK(hipMemcpyAsync(w.h_hist + 2 * slot, w.hist + 2 * (size_t)it, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            HIP_OK(hipEventRecord(w.ev[slot], s));
+            if (pending >= 0) {
+                HIP_OK(hipEventSynchronize(w.ev[pending]));
+                if (w.h_hist[2 * pending + 1] != 0.0) status = PA_ERR_BREAKDOWN;
+                else if (w.h_hist[2 * pending] <= tol2) status = PA_OK;
+                rr = w.h_hist[2 * pending];
+            }
+            pending = slot;
+        }
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    if (pending >= 0) {
+        const int ps = pending;
+        rr = w.h_hist[2 * ps];
+        if (w.h_hist[2 * ps + 1] != 0.0) status = PA_ERR_BREAKDOWN;
+        else if (rr <= tol2) status = PA_OK;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    res->seconds = std::chrono::duration<double>(t1 - t0).count();
+    res->iters = it;
+    res->rel_res_recursive = std::sqrt(rr) / bnorm;
+    // true residual in FP64
+    rc = con ? do_apply_constrained(op, x, w.Ap, s) : do_apply(op, op->variant, x, w.Ap, s);
+    if (rc) return rc;
+    HIP_OK(cg_init(b, w.Ap, w.r, nullptr, n, w.partial, w.sc, w.hist, s));
+    HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    res->rel_res_true = std::sqrt(w.h_hist[0]) / bnorm;
+    res->status = status;
+    if (status == PA_ERR_NOT_CONVERGED) set_error("cg_solve: max_it reached before rtol");
+    if (status == PA_ERR_BREAKDOWN) set_error("cg_solve: breakdown (p^T A p <= 0 or non-finite scalar)");
+    return status;
+    PA_CATCH
+}

@@ -1,0 +1,86 @@
+// Internal declarations of the hexpa library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hexpa.h"
+
+namespace hexpa {
+
+constexpr int kMaxP = 8;
+constexpr int kMaxD = kMaxP + 1;
+constexpr int kMaxQ = kMaxP + 2;
+
+// Thread-local error message for pa_last_error().
+void set_error(const std::string &msg);
+
+// 1-D tables (tables.cpp).
+struct Tables1D {
+    int p = 0, d = 0, q = 0;
+    std::vector<double> nodes, qpts, qwts;  // GLL nodes [d], Gauss points/weights [q] on [0,1]
+    std::vector<double> B, G;               // [q][d]: l_i(x_a), l_i'(x_a)
+};
+bool make_tables(int p, int q, Tables1D &t, std::string &err);
+
+// Device-side 1-D table block: B[q][d], G[q][d] packed (kMaxQ*kMaxD each).
+struct DevTables {
+    double B[kMaxQ * kMaxD];
+    double G[kMaxQ * kMaxD];
+    double w[kMaxQ];
+    double x[kMaxQ];
+    double nodes[kMaxD];
+};
+
+struct CoeffDev {
+    int32_t kind;
+    double value, amp, freq;
+    const double *grid;  // device
+    int32_t gx, gy, gz;
+};
+
+}  // namespace hexpa
+
+struct pa_op {
+    int p = 0, d = 0, q = 0, ops = 0, ncomp = 0;
+    int nelem = 0, ndof = 0, ness = 0;
+    int nx = 0, ny = 0, nz = 0;
+    int variant = PA_VARIANT_MFMA;
+    int device = 0;
+    int32_t *d_elem_dofs = nullptr;  // [nelem][d^3]
+    double *d_qdata = nullptr;       // [nelem][ncomp][q^3]
+    double *d_vert = nullptr;        // [nvert][3]
+    int32_t *d_hex = nullptr;        // [nelem][8]
+    int nvert = 0;
+    hexpa::DevTables *d_tab = nullptr;
+    double *d_grid = nullptr;        // coefficient grid (kept for pa_qpoints-free reuse)
+    int32_t *d_ess = nullptr;        // [ness]
+    // colour classes: elements of colour c are d_color_elems[color_off[c] .. color_off[c+1])
+    int32_t *d_color_elems = nullptr;
+    int color_off[9] = {0};
+    // handle-owned scratch for constrained apply and solvers
+    double *d_scratch = nullptr;
+    size_t scratch_len = 0;
+    hexpa::Tables1D tab;
+};
+
+namespace hexpa {
+// Kernel launchers (implemented in the .hip files).
+hipError_t launch_setup_qdata(const pa_op *op, const CoeffDev &cf, int *d_bad, hipStream_t s);
+hipError_t launch_qpoints(const pa_op *op, double *xyz, hipStream_t s);
+hipError_t launch_nodes(const pa_op *op, double *xyz, hipStream_t s);
+hipError_t launch_load(const pa_op *op, const double *fq, double *b, hipStream_t s);
+// apply: y += A x over the listed elements (elem_list == nullptr: all)
+hipError_t launch_apply(const pa_op *op, int variant, const double *x, double *y,
+                        const int32_t *elem_list, int nlist, hipStream_t s, bool *supported);
+hipError_t launch_diag(const pa_op *op, double *diag, hipStream_t s);
+hipError_t launch_debug_mfma(const double *A, const double *B, double *D, hipStream_t s);
+// vector kernels (k_vec.hip)
+hipError_t vec_fill(double *y, double v, int64_t n, hipStream_t s);
+hipError_t vec_copy(double *y, const double *x, int64_t n, hipStream_t s);
+hipError_t vec_zero_list(double *y, const int32_t *list, int n, hipStream_t s);
+hipError_t vec_copy_list(double *y, const double *x, const int32_t *list, int n, hipStream_t s);
+hipError_t vec_set_list(double *y, double v, const int32_t *list, int n, hipStream_t s);
+}  // namespace hexpa

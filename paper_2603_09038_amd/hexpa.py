@@ -1,0 +1,309 @@
+"""ctypes binding of libhexpa.so (argument marshalling only).
+
+Every call below forwards to the C function of the same name declared in
+``include/hexpa.h``; all arithmetic runs in the library's HIP kernels.  Device
+vectors are torch tensors on the GPU (float64, contiguous); the library works on
+the caller's current torch stream.  There is no CPU fallback: if the shared
+library is missing or fails to load, importing this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhexpa.so")
+
+PA_OK = 0
+PA_ERR_ARG, PA_ERR_HIP, PA_ERR_UNSUPPORTED, PA_ERR_MESH = -1, -2, -3, -4
+PA_ERR_NOT_CONVERGED, PA_ERR_BREAKDOWN, PA_ERR_IO = -5, -6, -7
+PA_MASS, PA_DIFFUSION = 1, 2
+PA_COEFF_CONST, PA_COEFF_SINE, PA_COEFF_GRID = 0, 1, 2
+PA_VARIANT_MFMA, PA_VARIANT_VALU, PA_VARIANT_MFMA_COLORED = 0, 1, 2
+PA_CG_PLAIN, PA_CG_JACOBI = 0, 1
+
+# every symbol include/hexpa.h declares
+EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_constrained", "pa_diag", "pa_load", "pa_qpoints", "pa_nodes",
+           "pa_get_elem_dofs", "pa_get_ess", "pa_set_variant", "pa_info", "pa_destroy", "pa_last_error",
+           "cg_solve", "pa_debug_mfma_f64")
+
+
+class HexpaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hexpa error {code}: {msg}")
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("nvert", ctypes.c_int32), ("vert_xyz", ctypes.c_void_p), ("nelem", ctypes.c_int32),
+                ("hex", ctypes.c_void_p), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("elem_dofs", ctypes.c_void_p), ("ndof", ctypes.c_int32), ("ess_mode", ctypes.c_int32),
+                ("ess_marker", ctypes.c_void_p)]
+
+
+class CoeffDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("value", ctypes.c_double), ("amp", ctypes.c_double),
+                ("freq", ctypes.c_double), ("grid", ctypes.c_void_p), ("gx", ctypes.c_int32),
+                ("gy", ctypes.c_int32), ("gz", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("p", "q1d", "ops", "nelem", "ndof", "ness", "ncomp", "variant",
+                                              "elems_per_block")] + \
+               [("qdata_bytes", ctypes.c_int64), ("map_bytes", ctypes.c_int64)]
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_it", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("constrained", ctypes.c_int32)]
+
+
+class CgResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res_recursive", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int
+    sig = {
+        "pa_setup": [ctypes.POINTER(MeshDesc), i32, i32, ctypes.POINTER(CoeffDesc), ctypes.c_uint32, vp,
+                     ctypes.POINTER(vp)],
+        "pa_apply": [vp, vp, vp, vp],
+        "pa_apply_add": [vp, vp, vp, vp],
+        "pa_apply_constrained": [vp, vp, vp, vp],
+        "pa_diag": [vp, vp, i32, vp],
+        "pa_load": [vp, vp, vp, vp],
+        "pa_qpoints": [vp, vp, vp],
+        "pa_nodes": [vp, vp, vp],
+        "pa_get_elem_dofs": [vp, vp],
+        "pa_get_ess": [vp, vp],
+        "pa_set_variant": [vp, i32],
+        "pa_info": [vp, ctypes.POINTER(Info)],
+        "cg_solve": [vp, vp, vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgResult), vp],
+        "pa_debug_mfma_f64": [vp, vp, vp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.pa_destroy.argtypes = [vp]
+    lib.pa_destroy.restype = None
+    lib.pa_last_error.argtypes = []
+    lib.pa_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc != PA_OK and rc not in allow:
+        raise HexpaError(rc, _lib.pa_last_error().decode())
+    return rc
+
+
+def _dptr(t, dtype=None, n=None):
+    """Device pointer of a contiguous CUDA tensor (checked)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ C-ABI mirrors
+def pa_setup(mesh, order, q1d, coeff=None, ops=PA_DIFFUSION, structured=True, elem_dofs=None, ndof=0,
+             ess_mode=0, ess_marker=None, stream=None):
+    """mesh: dict(n, vert[(nv,3)], hex[(ne,8)]).  coeff: None (=1) or dict(kind, value, amp, freq, grid)."""
+    vert = np.ascontiguousarray(mesh["vert"], dtype=np.float64)
+    hexes = np.ascontiguousarray(mesh["hex"], dtype=np.int32)
+    md = MeshDesc()
+    md.nvert, md.vert_xyz = vert.shape[0], vert.ctypes.data
+    md.nelem, md.hex = hexes.shape[0], hexes.ctypes.data
+    n = int(mesh.get("n", 0)) if structured else 0
+    md.nx = md.ny = md.nz = n
+    keep = [vert, hexes]
+    if elem_dofs is not None:
+        ed = np.ascontiguousarray(elem_dofs, dtype=np.int32)
+        keep.append(ed)
+        md.elem_dofs, md.ndof = ed.ctypes.data, int(ndof)
+    md.ess_mode = int(ess_mode)
+    if ess_marker is not None:
+        mk = np.ascontiguousarray(ess_marker, dtype=np.uint8)
+        keep.append(mk)
+        md.ess_marker = mk.ctypes.data
+    cd = None
+    if coeff is not None:
+        cd = CoeffDesc()
+        cd.kind = int(coeff.get("kind", PA_COEFF_CONST))
+        cd.value = float(coeff.get("value", 1.0))
+        cd.amp = float(coeff.get("amp", 0.0))
+        cd.freq = float(coeff.get("freq", 0.0))
+        if coeff.get("grid") is not None:
+            g = np.ascontiguousarray(coeff["grid"], dtype=np.float64)
+            keep.append(g)
+            cd.grid = g.ctypes.data
+            cd.gz, cd.gy, cd.gx = g.shape
+    h = ctypes.c_void_p()
+    _check(_lib.pa_setup(ctypes.byref(md), int(order), int(q1d), ctypes.byref(cd) if cd is not None else None,
+                         int(ops), _stream(stream), ctypes.byref(h)))
+    del keep
+    return h
+
+
+def pa_info(h):
+    info = Info()
+    _check(_lib.pa_info(h, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in Info._fields_}
+
+
+def pa_apply(h, x, y, stream=None):
+    _check(_lib.pa_apply(h, _dptr(x), _dptr(y), _stream(stream)))
+
+
+def pa_apply_add(h, x, y, stream=None):
+    _check(_lib.pa_apply_add(h, _dptr(x), _dptr(y), _stream(stream)))
+
+
+def pa_apply_constrained(h, x, y, stream=None):
+    _check(_lib.pa_apply_constrained(h, _dptr(x), _dptr(y), _stream(stream)))
+
+
+def pa_diag(h, d, constrained=False, stream=None):
+    _check(_lib.pa_diag(h, _dptr(d), int(bool(constrained)), _stream(stream)))
+
+
+def pa_load(h, f_qp, b, stream=None):
+    _check(_lib.pa_load(h, _dptr(f_qp), _dptr(b), _stream(stream)))
+
+
+def pa_qpoints(h, xyz, stream=None):
+    _check(_lib.pa_qpoints(h, _dptr(xyz), _stream(stream)))
+
+
+def pa_nodes(h, xyz, stream=None):
+    _check(_lib.pa_nodes(h, _dptr(xyz), _stream(stream)))
+
+
+def pa_get_elem_dofs(h):
+    info = pa_info(h)
+    d = info["p"] + 1
+    out = np.zeros((info["nelem"], d ** 3), dtype=np.int32)
+    _check(_lib.pa_get_elem_dofs(h, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def pa_get_ess(h):
+    info = pa_info(h)
+    out = np.zeros(max(info["ness"], 1), dtype=np.int32)
+    _check(_lib.pa_get_ess(h, out.ctypes.data_as(ctypes.c_void_p)))
+    return out[:info["ness"]]
+
+
+def pa_set_variant(h, variant):
+    _check(_lib.pa_set_variant(h, int(variant)))
+
+
+def pa_destroy(h):
+    _lib.pa_destroy(h)
+
+
+def cg_solve(h, b, x, rtol=1e-8, max_it=10000, mode=PA_CG_JACOBI, check_every=1, constrained=True,
+             stream=None, raise_on_fail=True):
+    o = CgOpts(float(rtol), int(max_it), int(mode), int(check_every), int(bool(constrained)))
+    r = CgResult()
+    rc = _lib.cg_solve(h, _dptr(b), _dptr(x), ctypes.byref(o), ctypes.byref(r), _stream(stream))
+    if raise_on_fail:
+        _check(rc)
+    return {"rc": rc, "iters": r.iters, "status": r.status, "rel_res_recursive": r.rel_res_recursive,
+            "rel_res_true": r.rel_res_true, "seconds": r.seconds}
+
+
+def pa_debug_mfma_f64(A, B, D, stream=None):
+    _check(_lib.pa_debug_mfma_f64(_dptr(A), _dptr(B), _dptr(D), _stream(stream)))
+
+
+# ------------------------------------------------------------------ convenience
+class PAOperator:
+    """Owns a pa_op handle; thin convenience over the C calls above."""
+
+    def __init__(self, mesh, order, q1d, coeff=None, ops=PA_DIFFUSION, ess_mode=0, **kw):
+        self.h = pa_setup(mesh, order, q1d, coeff=coeff, ops=ops, ess_mode=ess_mode, **kw)
+        self.info = pa_info(self.h)
+        self.ndof = self.info["ndof"]
+        self.nelem = self.info["nelem"]
+        self.p, self.q = order, q1d
+
+    def _vec(self, n=None):
+        import torch
+        return torch.empty(self.ndof if n is None else n, dtype=torch.float64, device="cuda")
+
+    def apply(self, x, y=None):
+        y = self._vec() if y is None else y
+        pa_apply(self.h, x, y)
+        return y
+
+    def apply_constrained(self, x, y=None):
+        y = self._vec() if y is None else y
+        pa_apply_constrained(self.h, x, y)
+        return y
+
+    def diag(self, constrained=False):
+        d = self._vec()
+        pa_diag(self.h, d, constrained)
+        return d
+
+    def qpoints(self):
+        xyz = self._vec(self.nelem * self.q ** 3 * 3)
+        pa_qpoints(self.h, xyz)
+        return xyz.view(self.nelem, self.q ** 3, 3)
+
+    def nodes(self):
+        xyz = self._vec(self.ndof * 3)
+        pa_nodes(self.h, xyz)
+        return xyz.view(self.ndof, 3)
+
+    def load(self, f_qp):
+        b = self._vec()
+        pa_load(self.h, f_qp.contiguous().view(-1), b)
+        return b
+
+    def set_variant(self, v):
+        pa_set_variant(self.h, v)
+        self.info = pa_info(self.h)
+
+    def cg(self, b, x=None, **kw):
+        import torch
+        x = torch.zeros_like(b) if x is None else x
+        res = cg_solve(self.h, b, x, **kw)
+        return x, res
+
+    def close(self):
+        if self.h:
+            pa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,194 @@
+"""Parity of the HIP path (through the C-ABI) against the CPU oracle, on MI355X.
+
+Bars: index maps bit-exact; FP64 apply/diag/load within 1e-12 relative in the 2-norm
+and the max-norm (the operator reaches the plain element-assembly result up to
+rounding order; 1e-12 leaves ~1e3-1e4 ulps of headroom for the different summation
+orders of sum factorization, MFMA accumulation and atomics).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def hx():
+    import torch  # noqa: F401
+    from paper_2603_09038_amd import hexpa
+    return hexpa
+
+
+def _cuda(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return max(np.linalg.norm(a - b) / np.linalg.norm(b), np.abs(a - b).max() / np.abs(b).max())
+
+
+def _ops_o(ops):
+    return (oracle.MASS if ops & 1 else 0) | (oracle.DIFFUSION if ops & 2 else 0)
+
+
+def test_mfma_f64_lane_layout(hx):
+    """One v_mfma_f64_16x16x4f64 against a CPU GEMM: pins the operand/result lane maps."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((16, 4))
+    B = rng.standard_normal((4, 16))
+    import torch
+    D = torch.zeros(256, dtype=torch.float64, device="cuda")
+    hx.pa_debug_mfma_f64(_cuda(A.ravel()), _cuda(B.ravel()), D)
+    np.testing.assert_allclose(D.cpu().numpy().reshape(16, 16), A @ B, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,p", [(4, 2), (3, 4), (2, 7)])
+def test_maps_bit_exact(hx, n, p):
+    mesh = synth.box_mesh(n)
+    op = hx.PAOperator(mesh, p, p + 2, ess_mode=1)
+    assert np.array_equal(hx.pa_get_elem_dofs(op.h), oracle.box_elem_dofs(n, p))
+    assert np.array_equal(hx.pa_get_ess(op.h), np.nonzero(oracle.box_boundary(n, p))[0].astype(np.int32))
+    op.close()
+
+
+@pytest.mark.parametrize("ops", [1, 2, 3])
+def test_c1_parity(hx, ops):
+    """4^3 perturbed unit cube, p=2, 4^3 Gauss points, kappa = 1, x ~ U[-1,1]: 729 DOFs."""
+    mesh = synth.box_mesh(4, perturb=0.1, seed=0)
+    op = hx.PAOperator(mesh, 2, 4, ops=ops)
+    assert op.ndof == 729
+    x = synth.rand_x(op.ndof, 0)
+    ref = oracle.Problem(mesh, 2, 4, ops=_ops_o(ops)).apply(x)
+    for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU, hx.PA_VARIANT_MFMA_COLORED):
+        op.set_variant(variant)
+        y = op.apply(_cuda(x)).cpu().numpy()
+        assert _rel(y, ref) <= TOL, (variant, _rel(y, ref))
+    op.close()
+
+
+# several element groups and a ragged tail at every order (n^3 is never a multiple of
+# the elements-per-workgroup count except by accident), both quadrature sizes
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("dq", [1, 2])
+def test_apply_parity_orders(hx, p, dq):
+    q = p + dq
+    n = {1: 7, 2: 5, 3: 4, 4: 3, 5: 3, 6: 2, 7: 2, 8: 2}[p]
+    mesh = synth.box_mesh(n, perturb=0.1, seed=p)
+    coeff = {"kind": hx.PA_COEFF_SINE, "value": 1.0, "amp": 0.5, "freq": 2.0}
+    for ops in (1, 2, 3):
+        op = hx.PAOperator(mesh, p, q, coeff=coeff, ops=ops)
+        x = synth.rand_x(op.ndof, p)
+        ref = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.sine(), ops=_ops_o(ops)).apply(x)
+        for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU):
+            op.set_variant(variant)
+            y = op.apply(_cuda(x)).cpu().numpy()
+            assert _rel(y, ref) <= TOL, (p, q, ops, variant, _rel(y, ref))
+        op.close()
+
+
+def test_grid_coefficient_and_diag_load_points(hx):
+    p, q, n = 3, 5, 3
+    mesh = synth.box_mesh(n, perturb=0.1, seed=9)
+    grid, _ = synth.lognormal_kappa_grid(4, sigma=1.0, ell=0.1, nfft=32)
+    op = hx.PAOperator(mesh, p, q, coeff={"kind": hx.PA_COEFF_GRID, "grid": grid}, ops=3, ess_mode=1)
+    P = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.from_grid(grid), ops=3)
+    x = synth.rand_x(op.ndof, 2)
+    assert _rel(op.apply(_cuda(x)).cpu().numpy(), P.apply(x)) <= TOL
+    assert _rel(op.diag().cpu().numpy(), P.diag()) <= TOL
+    xq = op.qpoints().cpu().numpy()
+    np.testing.assert_allclose(xq, P.qpoints(), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(op.nodes().cpu().numpy(), P.nodes(), rtol=0, atol=1e-15)
+    fq = synth.f_manufactured(xq.reshape(-1, 3)).reshape(P.nelem, -1)
+    assert _rel(op.load(_cuda(fq)).cpu().numpy(), P.load(fq)) <= TOL
+    # constrained apply / diag
+    ess = oracle.box_boundary(n, p).astype(bool)
+    from oracle import solvers
+    yc = op.apply_constrained(_cuda(x)).cpu().numpy()
+    assert _rel(yc, solvers.constrained(P.apply, ess)(x)) <= TOL
+    dc = op.diag(constrained=True).cpu().numpy()
+    assert _rel(dc, solvers.constrained_diag(P.diag(), ess)) <= TOL
+    op.close()
+
+
+def test_single_element_reconstructs_element_matrix(hx):
+    """n = 1: applying to unit vectors rebuilds A_e column by column."""
+    mesh = synth.box_mesh(1)
+    rng = np.random.default_rng(5)
+    mesh["vert"] = mesh["vert"] + rng.uniform(-0.1, 0.1, mesh["vert"].shape)
+    p, q = 3, 5
+    op = hx.PAOperator(mesh, p, q, ops=3)
+    Ae = oracle.Problem(mesh, p, q, ops=3).elem_matrices()[0]
+    import torch
+    I = torch.eye(op.ndof, dtype=torch.float64, device="cuda")
+    cols = np.stack([op.apply(I[k].contiguous()).cpu().numpy() for k in range(op.ndof)], 1)
+    assert np.abs(cols - Ae).max() <= TOL * np.abs(Ae).max()
+    op.close()
+
+
+def test_coloured_apply_is_bitwise_reproducible(hx):
+    mesh = synth.box_mesh(6, perturb=0.1, seed=1)
+    op = hx.PAOperator(mesh, 4, 6, ops=2)
+    op.set_variant(hx.PA_VARIANT_MFMA_COLORED)
+    x = _cuda(synth.rand_x(op.ndof, 3))
+    y1 = op.apply(x).cpu().numpy()
+    y2 = op.apply(x).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    op.set_variant(hx.PA_VARIANT_MFMA)
+    assert _rel(op.apply(x).cpu().numpy(), y1) <= TOL
+    op.close()
+
+
+def test_jacobi_pcg_true_residual_under_oracle(hx):
+    """C2-shaped problem at reduced size: sine coefficient, manufactured RHS, Dirichlet."""
+    n, p, q = 6, 4, 6
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    coeff = {"kind": hx.PA_COEFF_SINE, "value": 1.0, "amp": 0.5, "freq": 2.0}
+    op = hx.PAOperator(mesh, p, q, coeff=coeff, ops=2, ess_mode=1)
+    xq = op.qpoints().cpu().numpy().reshape(-1, 3)
+    b = op.load(_cuda(synth.f_manufactured(xq).reshape(op.nelem, -1)))
+    ess = hx.pa_get_ess(op.h)
+    import torch
+    b[torch.tensor(ess, device="cuda", dtype=torch.long)] = 0.0
+    x, res = op.cg(b, rtol=1e-8, max_it=2000, mode=hx.PA_CG_JACOBI)
+    assert res["rc"] == 0 and res["rel_res_true"] <= 1e-8
+    # judged by the oracle operator
+    P = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.sine(), ops=oracle.DIFFUSION)
+    from oracle import solvers
+    essm = oracle.box_boundary(n, p).astype(bool)
+    Ac = solvers.constrained(P.apply, essm)
+    bb = b.cpu().numpy()
+    xx = x.cpu().numpy()
+    assert np.linalg.norm(bb - Ac(xx)) <= 1.01e-8 * np.linalg.norm(bb)
+    # iteration count close to the oracle's PCG on the same system
+    dinv = 1.0 / solvers.constrained_diag(P.diag(), essm)
+    _, it_o, _, _, _ = solvers.pcg(Ac, bb, lambda r: dinv * r, rtol=1e-8)
+    assert abs(res["iters"] - it_o) <= 2 + 0.02 * it_o, (res["iters"], it_o)
+    op.close()
+
+
+def test_full_size_c2_sampled_rows(hx):
+    """48^3 perturbed mesh, p=4, Q=6, sine coefficient (7,189,057 DOFs), in the launch
+    configuration the benchmark times: sampled rows against the oracle's row evaluation."""
+    n, p, q = 48, 4, 6
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    coeff = {"kind": hx.PA_COEFF_SINE, "value": 1.0, "amp": 0.5, "freq": 2.0}
+    op = hx.PAOperator(mesh, p, q, coeff=coeff, ops=2)
+    assert op.ndof == 7189057
+    x = synth.rand_x(op.ndof, 0)
+    y = op.apply(_cuda(x)).cpu().numpy()
+    rows = np.unique(np.concatenate([np.random.default_rng(0).integers(0, op.ndof, 48), [0, op.ndof - 1]]))
+    P = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.sine(), ops=oracle.DIFFUSION)
+    ref = P.apply_rows(x, rows)
+    scale = np.abs(ref).max()
+    assert np.abs(y[rows] - ref).max() <= TOL * 10 * scale
+    # property at any size: K 1 = 0
+    import torch
+    one = torch.ones(op.ndof, dtype=torch.float64, device="cuda")
+    assert float(op.apply(one).abs().max()) <= 1e-12 * scale
+    op.close()
