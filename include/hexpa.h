@@ -171,8 +171,10 @@ int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
 
 /* ------------------------------------------------------------------ diagnostics */
 
-/* One v_mfma_f64_16x16x4f64 on the device: D[16][16] = A[16][4] * B[4][16] (row-major,
-   device pointers).  Used by the tests to pin the operand/lane layout the kernels assume. */
+/* One v_mfma_f64_16x16x4f64 on the device with A[16][4], B[4][16] (row-major, device
+   pointers; lane l supplies A[l%16][l/16] and B[l/16][l%16]).  Writes the raw accumulator
+   lane-major, Draw[4*l + v] (256 doubles), so a test can pin which entry of A*B each
+   lane/element holds: the layout the apply kernels assume. */
 int pa_debug_mfma_f64(const double *A, const double *B, double *D, void *stream);
 
 #ifdef __cplusplus

@@ -149,7 +149,7 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int o = rb * 16 + kl * 4 + v;
+                    const int o = rb * 16 + kl + 4 * v;  // f64 16x16x4 result: row l/16 + 4v
                     if (o < P::O) {
                         const int ad = P::out(o, n);
                         if (ad >= 0) out.put(e, ad, acc[rb][v]);

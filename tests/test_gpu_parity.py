@@ -38,14 +38,36 @@ def _ops_o(ops):
 
 
 def test_mfma_f64_lane_layout(hx):
-    """One v_mfma_f64_16x16x4f64 against a CPU GEMM: pins the operand/result lane maps."""
+    """One v_mfma_f64_16x16x4f64 against a CPU GEMM: pins the operand/result lane maps the
+    kernels assume (lane l, element v holds D[l/16 + 4v][l%16])."""
+    import torch
+    # structured operands: D[i][j] = j + 1000 i identifies every entry
+    A = np.zeros((16, 4))
+    A[:, 0], A[:, 1] = 1.0, np.arange(16)
+    B = np.zeros((4, 16))
+    B[0, :], B[1, :] = np.arange(16), 1000.0
+    raw = torch.zeros(256, dtype=torch.float64, device="cuda")
+    hx.pa_debug_mfma_f64(_cuda(A.ravel()), _cuda(B.ravel()), raw)
+    raw = raw.cpu().numpy().reshape(64, 4)
+    held = {(int(v) // 1000, int(v) % 1000) for v in raw.ravel()}
+    assert len(held) == 256  # every entry of D exactly once
+    rows, cols = raw // 1000, raw % 1000
+    lanes = np.arange(64)
+    assert np.array_equal(cols, np.repeat((lanes % 16)[:, None], 4, 1)), cols[::16]
+    expect = (lanes // 16)[:, None] + 4 * np.arange(4)[None, :]
+    assert np.array_equal(rows, expect), f"rows held by lanes 0,16,32,48: {rows[::16].tolist()}"
+    # random operands: the same map reproduces A @ B
     rng = np.random.default_rng(3)
     A = rng.standard_normal((16, 4))
     B = rng.standard_normal((4, 16))
-    import torch
-    D = torch.zeros(256, dtype=torch.float64, device="cuda")
-    hx.pa_debug_mfma_f64(_cuda(A.ravel()), _cuda(B.ravel()), D)
-    np.testing.assert_allclose(D.cpu().numpy().reshape(16, 16), A @ B, rtol=1e-14, atol=1e-14)
+    hx.pa_debug_mfma_f64(_cuda(A.ravel()), _cuda(B.ravel()), raw := torch.zeros(256, dtype=torch.float64,
+                                                                                 device="cuda"))
+    raw = raw.cpu().numpy().reshape(64, 4)
+    D = np.zeros((16, 16))
+    for l in range(64):
+        for v in range(4):
+            D[l // 16 + 4 * v, l % 16] = raw[l, v]
+    np.testing.assert_allclose(D, A @ B, rtol=1e-14, atol=1e-14)
 
 
 @pytest.mark.parametrize("n,p", [(4, 2), (3, 4), (2, 7)])
