@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--variant", default="mfma", choices=["mfma", "valu", "colored"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "mfma", "valu", "colored"])
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0 = skip)")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--sweep", action="store_true")
@@ -122,8 +122,11 @@ def main():
     mesh = synth.box_mesh(n, perturb=0.1, seed=0)
     coeff = {"kind": hexpa.PA_COEFF_SINE, "value": 1.0, "amp": 0.5, "freq": 2.0}
     op = hexpa.PAOperator(mesh, p, q, coeff=coeff, ops=hexpa.PA_DIFFUSION)
-    op.set_variant({"mfma": hexpa.PA_VARIANT_MFMA, "valu": hexpa.PA_VARIANT_VALU,
-                    "colored": hexpa.PA_VARIANT_MFMA_COLORED}[args.variant])
+    VAR = {"mfma": hexpa.PA_VARIANT_MFMA, "valu": hexpa.PA_VARIANT_VALU, "colored": hexpa.PA_VARIANT_MFMA_COLORED}
+    VNAME = {v: k for k, v in VAR.items()}
+    if args.variant != "auto":
+        op.set_variant(VAR[args.variant])
+    used = VNAME[op.info["variant"]]
     ndof, nelem = op.ndof, op.nelem
     x = torch.tensor(synth.rand_x(ndof, 0), device="cuda")
     y = torch.empty_like(x)
@@ -151,10 +154,10 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "fp64 PA diffusion apply, 48^3 perturbed hex mesh, p=4, Q=6, "
                                "kappa=1+0.5sin(2pi x)sin(2pi y)sin(2pi z), x~U[-1,1]",
-                   "ndof": ndof, "nelem": nelem, "p": p, "q1d": q, "variant": args.variant},
+                   "ndof": ndof, "nelem": nelem, "p": p, "q1d": q, "variant": used},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_apply<5,6,2,mfma>", "alg_bytes_per_launch": ab,
+                     "kernel": f"k_apply<D=5,Q=6,diffusion,{used}>", "alg_bytes_per_launch": ab,
                      "alg_bytes_per_dof": ab / ndof, "kernel_ms_mean": k_mean_ms, "kernel_ms_median": k_med_ms,
                      "kernel_gdofs": ndof / (k_mean_ms * 1e-3) / 1e9,
                      "fp64_frac": alg_flops(nelem, p, q, 2) / (k_mean_ms * 1e-3) / 78.6e12},
@@ -168,14 +171,16 @@ def main():
             m2 = synth.box_mesh(nn, perturb=0.1, seed=0)
             for ops in (hexpa.PA_MASS, hexpa.PA_DIFFUSION):
                 o2 = hexpa.PAOperator(m2, pp, pp + 2, ops=ops)
-                o2.set_variant({"mfma": 0, "valu": 1, "colored": 2}[args.variant])
+                if args.variant != "auto":
+                    o2.set_variant(VAR[args.variant])
                 x2 = torch.tensor(synth.rand_x(o2.ndof, 0), device="cuda")
                 y2 = torch.empty_like(x2)
                 km, _ = time_kernel(o2, hexpa, x2, y2, 20, 5)
                 ab2 = alg_bytes(o2.ndof, o2.nelem, pp, pp + 2, ops)
                 sweep.append({"p": pp, "n": nn, "op": "mass" if ops == 1 else "diffusion", "ndof": o2.ndof,
                               "kernel_ms": km, "gdofs": o2.ndof / (km * 1e-3) / 1e9,
-                              "hbm_frac": ab2 / (km * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                              "hbm_frac": ab2 / (km * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "variant": VNAME[o2.info["variant"]]})
                 o2.close()
                 del x2, y2
                 torch.cuda.empty_cache()

@@ -78,8 +78,9 @@ typedef struct {
     int32_t gx, gy, gz;
 } pa_coeff_desc;
 
-/* Apply-kernel variants (pa_set_variant). */
-#define PA_VARIANT_MFMA 0    /* fused kernel, FP64 MFMA contractions, atomic scatter (default) */
+/* Apply-kernel variants (pa_set_variant).  pa_setup selects the faster contraction unit
+   measured on MI355X for the order: VALU for p <= 4, MFMA for p >= 5. */
+#define PA_VARIANT_MFMA 0    /* fused kernel, FP64 MFMA contractions, atomic scatter */
 #define PA_VARIANT_VALU 1    /* fused kernel, FP64 vector-ALU contractions, atomic scatter */
 #define PA_VARIANT_MFMA_COLORED 2 /* MFMA contractions, 8 colour launches, plain read-modify-write
                                      scatter: bitwise reproducible */
@@ -171,11 +172,15 @@ int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
 
 /* ------------------------------------------------------------------ diagnostics */
 
-/* One v_mfma_f64_16x16x4f64 on the device with A[16][4], B[4][16] (row-major, device
-   pointers; lane l supplies A[l%16][l/16] and B[l/16][l%16]).  Writes the raw accumulator
-   lane-major, Draw[4*l + v] (256 doubles), so a test can pin which entry of A*B each
-   lane/element holds: the layout the apply kernels assume. */
-int pa_debug_mfma_f64(const double *A, const double *B, double *D, void *stream);
+/* One FP64 MFMA on the device, writing the raw accumulator so a test can pin which entry
+   of the product each lane holds (the layout the apply kernels assume).  Device pointers.
+   shape 16: v_mfma_f64_16x16x4f64 with A[16][4], B[4][16] row-major; lane l supplies
+             A[l%16][l/16] and B[l/16][l%16]; writes Draw[4*l + v] (256 doubles).
+   shape 4:  v_mfma_f64_4x4x4f64 (four 4x4x4 blocks) with A[4][4][4], B[4][4][4] (block,
+             row, col); lane l supplies A[b][l&3][l>>4] and B[b][l>>4][l&3] with
+             b = (l>>2)&3; writes Draw[l] (64 doubles).
+   Returns PA_ERR_ARG for another shape. */
+int pa_debug_mfma_f64(int shape, const double *A, const double *B, double *D, void *stream);
 
 #ifdef __cplusplus
 }

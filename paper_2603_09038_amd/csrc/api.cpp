@@ -126,6 +126,8 @@ extern "C" int pa_setup(const pa_mesh_desc *m, int order, int q1d, const pa_coef
 
     std::unique_ptr<pa_op, void (*)(pa_op *)> op(new pa_op, pa_destroy);
     op->p = order; op->d = order + 1; op->q = q1d; op->ops = (int)ops;
+    // default contraction unit: the faster one measured on MI355X for this order
+    op->variant = order <= 4 ? PA_VARIANT_VALU : PA_VARIANT_MFMA;
     op->ncomp = (ops & PA_DIFFUSION) ? ((ops & PA_MASS) ? 7 : 6) : 1;
     op->nelem = m->nelem; op->nvert = m->nvert;
     std::string terr;
@@ -406,10 +408,11 @@ extern "C" int pa_info(const pa_op *op, pa_info_t *info)
     return PA_OK;
 }
 
-extern "C" int pa_debug_mfma_f64(const double *A, const double *B, double *D, void *stream)
+extern "C" int pa_debug_mfma_f64(int shape, const double *A, const double *B, double *D, void *stream)
 {
     if (!A || !B || !D) return arg_error("pa_debug_mfma_f64: NULL argument");
-    HIP_OK(launch_debug_mfma(A, B, D, as_stream(stream)));
+    if (shape != 4 && shape != 16) return arg_error("pa_debug_mfma_f64: shape must be 4 or 16");
+    HIP_OK(launch_debug_mfma(shape, A, B, D, as_stream(stream)));
     return PA_OK;
 }
 

@@ -16,9 +16,9 @@
 // fastest in memory, so the input of every pass is In[n][k] with unit stride in k.
 //
 // Two executors consume the same pass descriptors:
-//   * MFMA: v_mfma_f64_16x16x4f64 with A (the 1-D basis) resident in VGPRs as the
-//     16x4 A-operand, 16 GEMM columns (n, across the E elements) per tile as the 4x16
-//     B-operand read from LDS, and 16 output rows per row block;
+//   * MFMA: v_mfma_f64_4x4x4f64 (four 4x4x4 blocks = a 4x16x4 GEMM slice) with A (the
+//     1-D basis) as the A-operand in VGPRs, 16 GEMM columns (n, across the E elements)
+//     per tile as the B-operand read from LDS, and 4 output rows per row tile;
 //   * VALU: one thread per GEMM column, all O outputs in registers, A read with uniform
 //     (scalar) loads.
 #pragma once
@@ -30,8 +30,25 @@
 
 namespace hexpa {
 
-constexpr int kThreads = 256;
+#ifndef HEXPA_THREADS
+#define HEXPA_THREADS 256
+#endif
+constexpr int kThreads = HEXPA_THREADS;  // threads per workgroup of the fused apply
 constexpr int kWaves = kThreads / 64;
+
+// Tuning constants (overridable at compile time for sweeps).
+#ifndef HEXPA_LDS_BUDGET
+#define HEXPA_LDS_BUDGET (48 * 1024)
+#endif
+#ifndef HEXPA_MFMA_BATCH
+#define HEXPA_MFMA_BATCH 2
+#endif
+#ifndef HEXPA_VALU_BATCH
+#define HEXPA_VALU_BATCH 2
+#endif
+constexpr int kLdsBudget = HEXPA_LDS_BUDGET;  // bytes of LDS per workgroup
+constexpr int kMfmaBatch = HEXPA_MFMA_BATCH;  // MFMA tiles in flight per wave
+constexpr int kValuBatch = HEXPA_VALU_BATCH;  // GEMM columns in flight per thread
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -56,9 +73,10 @@ struct Shape {
     // ping-pong LDS regions per element (doubles); odd strides spread elements over banks
     static constexpr int SZ_A = cmax3(SZ_X, SZ_U2, SZ_W) | 1;
     static constexpr int SZ_B = cmax3(SZ_U1, SZ_G3, SZ_T) | 1;
+    static constexpr int SLACK = 16 * 2 * kMaxQ;  // tail of each buffer for padded tile columns
     static constexpr int PER_ELEM_BYTES = 8 * (SZ_A + SZ_B) + 4 * D3;
-    // elements per workgroup: ~48 KB of LDS per group -> 3 groups per CU (160 KB)
-    static constexpr int E = cclamp((48 * 1024) / PER_ELEM_BYTES, 1, 32);
+    // elements per workgroup from the LDS budget (48 KB -> 3 workgroups per 160 KB CU)
+    static constexpr int E = cclamp(kLdsBudget / PER_ELEM_BYTES, 1, 32);
     static constexpr int NS = (E * Q3 + kThreads - 1) / kThreads;  // qp slots per thread
 };
 
@@ -67,29 +85,37 @@ __device__ __forceinline__ double tB(const DevTables *t, int a, int i, int D) { 
 __device__ __forceinline__ double tG(const DevTables *t, int a, int i, int D) { return t->G[a * D + i]; }
 
 // ------------------------------------------------------------------ MFMA executor
+// v_mfma_f64_4x4x4f64 computes four independent 4x4x4 products; block beta = (l>>2)&3
+// takes its A-operand from lane l as A_beta[l&3][l>>4], its B-operand as B_beta[l>>4][l&3]
+// and returns D_beta[l>>4][l&3] in lane l (pinned by test_mfma_f64_lane_layouts).  With
+// the same A in every block, the four blocks are one 4 (rows) x 16 (columns) x 4 (k) GEMM
+// slice: column n = l & 15, contracted index k = l >> 4, output row l >> 4.  On gfx950
+// this shape sustains ~1.4x the FP64 rate of v_mfma_f64_16x16x4f64 and pads the small
+// 1-D dimensions (d = p+1, Q) to multiples of 4 instead of 16.
 template <class P>
 struct PassRegs {
     static constexpr int K = P::NT * P::C;
-    static constexpr int KC = (K + 3) / 4;
-    static constexpr int RB = (P::O + 15) / 16;
+    static constexpr int KC = (K + 3) / 4;   // k chunks of 4
+    static constexpr int RT = (P::O + 3) / 4;  // 4-row tiles
 };
 
-// A operand: lane l holds A[rb*16 + l%16][4*kc + l/16] of the stacked pass matrix.
+// A operand: lane l holds A[4 rt + (l & 3)][4 kc + (l >> 4)] of the stacked pass matrix.
 template <class P>
-__device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassRegs<P>::RB][PassRegs<P>::KC], int lane)
+__device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassRegs<P>::RT][PassRegs<P>::KC], int lane)
 {
     constexpr int K = PassRegs<P>::K;
 #pragma unroll
-    for (int rb = 0; rb < PassRegs<P>::RB; ++rb)
+    for (int rt = 0; rt < PassRegs<P>::RT; ++rt)
 #pragma unroll
         for (int kc = 0; kc < PassRegs<P>::KC; ++kc) {
-            const int o = rb * 16 + (lane & 15);
+            const int o = 4 * rt + (lane & 3);
             const int k = 4 * kc + (lane >> 4);
-            a[rb][kc] = (o < P::O && k < K) ? P::A(tab, o, k) : 0.0;
+            a[rt][kc] = (o < P::O && k < K) ? P::A(tab, o, k) : 0.0;
         }
 }
 
 // Store policy of a pass output: into LDS, or atomically / plainly into the global y.
+// `addr` is element-local (OUT + n + NCOL o).
 struct LdsOut {
     double *out;
     int sz;
@@ -112,77 +138,123 @@ struct GlobalOut {
     }
 };
 
+// Columns are padded to NCOLP (a multiple of 16) per element so that a 16-column tile
+// never straddles two elements: tile t covers element t / TPE, columns
+// n0 = 16 (t % TPE) .. n0 + 15.  Tiles are dealt to the waves round-robin; the tile
+// index is wave-uniform, so the element/column bases are scalar values and each lane
+// adds one lane-constant offset per tile -- no per-element index arithmetic.  Padding
+// columns (n >= NCOL) read inside the buffer slack and are never stored.
+template <class P>
+struct Tiling {
+    static constexpr int NCOLP = (P::NCOL + 15) / 16 * 16;
+    static constexpr int TPE = NCOLP / 16;
+};
+
 template <class P, int E, class Out>
 __device__ __forceinline__ void mfma_pass(const double *in, int szin,
-                                          const double (&a)[PassRegs<P>::RB][PassRegs<P>::KC],
+                                          const double (&a)[PassRegs<P>::RT][PassRegs<P>::KC],
                                           const Out &out, int wave, int lane)
 {
-    constexpr int C = P::C, K = PassRegs<P>::K, KC = PassRegs<P>::KC, RB = PassRegs<P>::RB;
-    constexpr int NTOT = E * P::NCOL;
-    constexpr int NTILE = (NTOT + 15) / 16;
+    constexpr int C = P::C, K = PassRegs<P>::K, KC = PassRegs<P>::KC, RT = PassRegs<P>::RT;
+    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE;
+    constexpr int NR = (NTILE + kWaves - 1) / kWaves;
+    constexpr int BATCH = NR < kMfmaBatch ? NR : kMfmaBatch;
     const int kl = lane >> 4, nl = lane & 15;
-    int koff[KC];
+    // lane constants: B-operand offsets per k chunk, output offset of row kl
+    int lin[KC];
     bool kval[KC];
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
         const int k = 4 * kc + kl;
         kval[kc] = k < K;
         const int t = k / C, c = k - t * C;
-        koff[kc] = kval[kc] ? P::in_off(t) + c : 0;
+        lin[kc] = nl * C + (kval[kc] ? P::in_off(t) + c : 0);
     }
-    for (int tile = wave; tile < NTILE; tile += kWaves) {
-        const int col = tile * 16 + nl;
-        const bool cval = col < NTOT;
-        const int e = col / P::NCOL, n = col - e * P::NCOL;
-        const double *base = in + e * szin + n * C;
-        dbl4 acc[RB];
+    const int lout = P::OUT + nl + P::NCOL * kl;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NR; r0 += BATCH) {
+        double bv[BATCH][KC];
+        int eS[BATCH], n0S[BATCH];
+        bool cv[BATCH];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[rb] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int bi = 0; bi < BATCH; ++bi) {
+            const int t = wave + kWaves * (r0 + bi);  // wave-uniform
+            const bool tv = (r0 + bi < NR) && t < NTILE;
+            const int e = tv ? t / TPE : 0;
+            const int n0 = tv ? (t - e * TPE) * 16 : 0;
+            eS[bi] = e;
+            n0S[bi] = n0;
+            cv[bi] = tv && (n0 + nl < P::NCOL);
+            const double *base = in + e * szin + n0 * C;
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            const double b = (cval && kval[kc]) ? base[koff[kc]] : 0.0;
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb][kc], b, acc[rb], 0, 0, 0);
+            for (int kc = 0; kc < KC; ++kc) {
+                const double v = base[lin[kc]];
+                bv[bi][kc] = (cv[bi] && kval[kc]) ? v : 0.0;
+            }
         }
-        if (cval) {
+        double acc[BATCH][RT];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
+        for (int bi = 0; bi < BATCH; ++bi)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int o = rb * 16 + kl + 4 * v;  // f64 16x16x4 result: row l/16 + 4v
-                    if (o < P::O) {
-                        const int ad = P::out(o, n);
-                        if (ad >= 0) out.put(e, ad, acc[rb][v]);
-                    }
-                }
+            for (int rt = 0; rt < RT; ++rt) acc[bi][rt] = 0.0;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int bi = 0; bi < BATCH; ++bi)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[bi][rt] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[rt][kc], bv[bi][kc], acc[bi][rt], 0, 0, 0);
+#pragma unroll
+        for (int bi = 0; bi < BATCH; ++bi) {
+            if (!cv[bi]) continue;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                if (4 * rt + kl < P::O) out.put(eS[bi], n0S[bi] + lout + 4 * rt * P::NCOL, acc[bi][rt]);
         }
     }
 }
 
 // ------------------------------------------------------------------ VALU executor
+// One thread per GEMM column, all O outputs in registers; BATCH columns per thread are
+// loaded before any FMA so the LDS latency of one column hides behind another.
 template <class P, int E, class Out>
 __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevTables *tab, const Out &out, int tid)
 {
     constexpr int C = P::C, NT = P::NT, O = P::O;
     constexpr int NTOT = E * P::NCOL;
-    for (int col = tid; col < NTOT; col += kThreads) {
-        const int e = col / P::NCOL, n = col - e * P::NCOL;
-        const double *base = in + e * szin + n * C;
-        double acc[O];
+    constexpr int NR = (NTOT + kThreads - 1) / kThreads;
+    constexpr int BATCH = NR < kValuBatch ? NR : kValuBatch;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NR; r0 += BATCH) {
+        double xin[BATCH][NT * C];
+        int eI[BATCH], nI[BATCH];
+        bool cv[BATCH];
 #pragma unroll
-        for (int o = 0; o < O; ++o) acc[o] = 0.0;
+        for (int bi = 0; bi < BATCH; ++bi) {
+            const int col = tid + kThreads * (r0 + bi);
+            cv[bi] = (r0 + bi < NR) && col < NTOT;
+            const int cc = cv[bi] ? col : 0;
+            eI[bi] = cc / P::NCOL;
+            nI[bi] = cc - eI[bi] * P::NCOL;
+            const double *base = in + eI[bi] * szin + nI[bi] * C;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const double v = base[P::in_off(t) + c];
+                for (int c = 0; c < C; ++c) xin[bi][t * C + c] = base[P::in_off(t) + c];
+        }
 #pragma unroll
-                for (int o = 0; o < O; ++o) acc[o] = fma(P::A(tab, o, t * C + c), v, acc[o]);
+        for (int bi = 0; bi < BATCH; ++bi) {
+            double acc[O];
+#pragma unroll
+            for (int o = 0; o < O; ++o) acc[o] = 0.0;
+#pragma unroll
+            for (int k = 0; k < NT * C; ++k)
+#pragma unroll
+                for (int o = 0; o < O; ++o) acc[o] = fma(P::A(tab, o, k), xin[bi][k], acc[o]);
+            if (cv[bi]) {
+#pragma unroll
+                for (int o = 0; o < O; ++o) out.put(eI[bi], P::OUT + nI[bi] + P::NCOL * o, acc[o]);
             }
-#pragma unroll
-        for (int o = 0; o < O; ++o) {
-            const int ad = P::out(o, n);
-            if (ad >= 0) out.put(e, ad, acc[o]);
         }
     }
 }

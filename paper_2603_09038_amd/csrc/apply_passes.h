@@ -2,176 +2,153 @@
 //
 // Notation per element: d = D nodes and Q Gauss points per axis; reference-gradient
 // channels at a quadrature point (a,b,c) are dx = G_x B_y B_z u, dy = B_x G_y B_z u,
-// dz = B_x B_y G_z u and, when the mass term is present, the value u = B_x B_y B_z u.
+// dz = B_x B_y G_z u and, with the mass term, the value u = B_x B_y B_z u.
 //
-// Each descriptor provides
-//   NCOL       GEMM columns per element (the two untouched tensor indices),
+// Every pass is a plain GEMM per element, Out[o][n] = sum_k A[o][k] In[n][k]:
+//   NCOL       GEMM columns per element (the two untouched tensor indices, n),
 //   C, NT      length of the contracted index and number of K-stacked input tensors,
-//   O          output rows (the new 1-D index; 2Q when B and G rows are stacked),
-//   in_off(t)  offset of input tensor t inside the element's input region,
-//   A(tab,o,k) the stacked pass matrix (k = t*C + c),
-//   out(o,n)   element-local output address, or -1 to drop the row/column pair.
+//   O          output rows (the new 1-D index; 2Q when the B and G rows are stacked),
+//   in_off(t)  offset of input tensor t inside the element's input region (In[n][c] at
+//              in_off(t) + n C + c),
+//   A(tab,o,k) the stacked pass matrix (k = t C + c),
+//   OUT        offset of the output inside the element's output region: Out[o][n] is
+//              stored at OUT + n + NCOL o.
+// Because each stage stores its output as [o][n], the next stage's contracted index is
+// the fastest one in memory (the cyclic index order of the paper's Sec. III-D), and a
+// block of rows of one pass (e.g. its G rows) is itself a contiguous tensor.
 #pragma once
 #include "apply_common.h"
 
 namespace hexpa {
 
+// Channel layout of the quadrature-point tensor V (element region of buffer B):
+// dx at 0, dy at Q^3; without the mass term dz at 2Q^3; with it u at 2Q^3 and dz at 3Q^3.
+template <int Q, bool M>
+struct Chan {
+    static constexpr int Q3 = Q * Q * Q;
+    static constexpr int X = 0, Y = Q3, V = 2 * Q3, Z = (M ? 3 : 2) * Q3;
+};
+
 // ======================================================================== diffusion
-// Forward stage x: X[n=(j,k)][i] -> U1[o1][n], rows o1 < Q: B, o1 >= Q: G.
+// Forward x: X[n=(j,k)][i] -> U1[o1][n]: rows o1 < Q are B_x X (BX), rows >= Q are G_x X (GX).
 template <int D, int Q, bool M>
 struct DF1 {
-    static constexpr int NCOL = D * D, C = D, NT = 1, O = 2 * Q;
-    __device__ static int in_off(int) { return 0; }
+    static constexpr int NCOL = D * D, C = D, NT = 1, O = 2 * Q, OUT = 0;
+    __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return o < Q ? tB(t, o, k, D) : tG(t, o - Q, k, D); }
-    __device__ static int out(int o, int n) { return n + NCOL * o; }
 };
-// Forward stage y: U1[n=(k,o1)][j] -> U2[m(o1,o2)][k]; the (G,G) combinations are dropped:
-// m = o1 + 2Q o2 for o2 < Q, and 2Q^2 + o1 + Q (o2 - Q) for o2 >= Q, o1 < Q.
+// Forward y on BX: BX[n=(k,a)][j] -> rows o2 < Q: T_BB = B_y BX, rows >= Q: T_BG = G_y BX.
 template <int D, int Q, bool M>
-struct DF2 {
-    static constexpr int NCOL = 2 * Q * D, C = D, NT = 1, O = 2 * Q;
-    __device__ static int in_off(int) { return 0; }
+struct DF2a {
+    static constexpr int NCOL = Q * D, C = D, NT = 1, O = 2 * Q, OUT = 0;
+    __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return o < Q ? tB(t, o, k, D) : tG(t, o - Q, k, D); }
-    __device__ static int out(int o2, int n)
+};
+// Forward y on GX: T_GB = B_y GX.
+template <int D, int Q, bool M>
+struct DF2b {
+    static constexpr int NCOL = Q * D, C = D, NT = 1, O = Q, OUT = 2 * Q * Q * D;
+    __device__ static constexpr int in_off(int) { return Q * D * D; }
+    __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
+};
+// Forward z on T_BB[n=(a,b)][k]: dz = G_z T_BB (and u = B_z T_BB, stacked first, with mass).
+template <int D, int Q, bool M>
+struct DF3a {
+    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = M ? 2 * Q : Q, OUT = M ? Chan<Q, M>::V : Chan<Q, M>::Z;
+    __device__ static constexpr int in_off(int) { return 0; }
+    __device__ static double A(const DevTables *t, int o, int k)
     {
-        const int o1 = n / D, k = n - o1 * D;
-        int m;
-        if (o2 < Q)
-            m = o1 + 2 * Q * o2;
-        else if (o1 < Q)
-            m = 2 * Q * Q + o1 + Q * (o2 - Q);
-        else
-            return -1;
-        return k + D * m;
+        return M ? (o < Q ? tB(t, o, k, D) : tG(t, o - Q, k, D)) : tG(t, o, k, D);
     }
 };
-// Forward stage z: U2[m][k] -> channels V[ch][c][b][a]; exactly one G among (o1,o2,o3)
-// gives dx/dy/dz, none gives the value channel (kept only with the mass term).
+// Forward z on T_BG: dy = B_z T_BG.
 template <int D, int Q, bool M>
-struct DF3 {
-    static constexpr int NCOL = 3 * Q * Q, C = D, NT = 1, O = 2 * Q;
-    __device__ static int in_off(int) { return 0; }
-    __device__ static double A(const DevTables *t, int o, int k) { return o < Q ? tB(t, o, k, D) : tG(t, o - Q, k, D); }
-    __device__ static int out(int o3, int m)
-    {
-        int o1, o2;
-        if (m < 2 * Q * Q) {
-            o2 = m / (2 * Q);
-            o1 = m - o2 * 2 * Q;
-        } else {
-            const int mm = m - 2 * Q * Q;
-            const int r = mm / Q;
-            o1 = mm - r * Q;
-            o2 = Q + r;
-        }
-        const int gx = o1 >= Q, gy = o2 >= Q, gz = o3 >= Q;
-        const int a = o1 - gx * Q, b = o2 - gy * Q, c = o3 - gz * Q;
-        int ch;
-        if (gx + gy + gz == 1)
-            ch = gx ? 0 : (gy ? 1 : 2);
-        else if (gx + gy + gz == 0 && M)
-            ch = 3;
-        else
-            return -1;
-        return ch * Q * Q * Q + a + Q * (b + Q * c);
-    }
+struct DF3b {
+    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = Q, OUT = Chan<Q, M>::Y;
+    __device__ static constexpr int in_off(int) { return Q * Q * D; }
+    __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
-// Transposed stage x, channel dx: V0[n=(b,c)][a] -> W0[i][n] with G^T.
+// Forward z on T_GB: dx = B_z T_GB.
 template <int D, int Q, bool M>
-struct DT1a {
-    static constexpr int NCOL = Q * Q, C = Q, NT = 1, O = D;
-    __device__ static int in_off(int) { return 0; }
-    __device__ static double A(const DevTables *t, int o, int k) { return tG(t, k, o, D); }
-    __device__ static int out(int o, int n) { return n + Q * Q * o; }
+struct DF3c {
+    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = Q, OUT = Chan<Q, M>::X;
+    __device__ static constexpr int in_off(int) { return 2 * Q * Q * D; }
+    __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
-// Transposed stage x, channels dy, dz (and value): B^T; W_ch[i][n] at ch*Q*Q*D.
-template <int D, int Q, bool M>
-struct DT1b {
-    static constexpr int NCH = M ? 3 : 2;
-    static constexpr int NCOL = NCH * Q * Q, C = Q, NT = 1, O = D;
-    __device__ static int in_off(int) { return Q * Q * Q; }
-    __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
-    __device__ static int out(int o, int n)
-    {
-        const int ch = 1 + n / (Q * Q), nn = n - (ch - 1) * Q * Q;
-        return ch * Q * Q * D + nn + Q * Q * o;
-    }
+// Transposed x of one channel: V_ch[n=(b,c)][a] -> W_slot[i][n] with G^T (dx) or B^T.
+template <int D, int Q, bool M, int CH_OFF, int SLOT, bool GT>
+struct DT1 {
+    static constexpr int NCOL = Q * Q, C = Q, NT = 1, O = D, OUT = SLOT * Q * Q * D;
+    __device__ static constexpr int in_off(int) { return CH_OFF; }
+    __device__ static double A(const DevTables *t, int o, int k) { return GT ? tG(t, k, o, D) : tB(t, k, o, D); }
 };
-// Transposed stage y, path continuing with B_z^T: t1 = B_y^T W0 + G_y^T W1 (+ B_y^T W3).
+// W slots in buffer A: 0 = dx, 1 = dy, 2 = dz, 3 = u.
+// Transposed y, path continuing with B_z^T: t1 = B_y^T W0 + G_y^T W1 (+ B_y^T W3).
 template <int D, int Q, bool M>
 struct DT2a {
-    static constexpr int NCOL = Q * D, C = Q, NT = M ? 3 : 2, O = D;
-    __device__ static int in_off(int t) { return (t == 2 ? 3 : t) * Q * Q * D; }
+    static constexpr int NCOL = Q * D, C = Q, NT = M ? 3 : 2, O = D, OUT = 0;
+    __device__ static constexpr int in_off(int t) { return (t == 2 ? 3 : t) * Q * Q * D; }
     __device__ static double A(const DevTables *tb, int o, int k)
     {
         const int t = k / Q, b = k - t * Q;
         return t == 1 ? tG(tb, b, o, D) : tB(tb, b, o, D);
     }
-    __device__ static int out(int o, int n) { return n + Q * D * o; }
 };
-// Transposed stage y, path continuing with G_z^T: t2 = B_y^T W2.
+// Transposed y, path continuing with G_z^T: t2 = B_y^T W2.
 template <int D, int Q, bool M>
 struct DT2b {
-    static constexpr int NCOL = Q * D, C = Q, NT = 1, O = D;
-    __device__ static int in_off(int) { return 2 * Q * Q * D; }
+    static constexpr int NCOL = Q * D, C = Q, NT = 1, O = D, OUT = D * D * Q;
+    __device__ static constexpr int in_off(int) { return 2 * Q * Q * D; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
-    __device__ static int out(int o, int n) { return D * D * Q + n + Q * D * o; }
 };
-// Transposed stage z: y_E[k][n=(i,j)] = B_z^T t1 + G_z^T t2 (K-stacked), scattered to y.
+// Transposed z: y_E[k][n=(i,j)] = B_z^T t1 + G_z^T t2 (K-stacked), scattered to y.
 template <int D, int Q, bool M>
 struct DT3 {
-    static constexpr int NCOL = D * D, C = Q, NT = 2, O = D;
-    __device__ static int in_off(int t) { return t * Q * D * D; }
+    static constexpr int NCOL = D * D, C = Q, NT = 2, O = D, OUT = 0;
+    __device__ static constexpr int in_off(int t) { return t * Q * D * D; }
     __device__ static double A(const DevTables *tb, int o, int k)
     {
         const int t = k / Q, c = k - t * Q;
         return t == 0 ? tB(tb, c, o, D) : tG(tb, c, o, D);
     }
-    __device__ static int out(int o, int n) { return n + D * D * o; }
 };
 
 // ======================================================================== mass
 template <int D, int Q>
 struct MF1 {
-    static constexpr int NCOL = D * D, C = D, NT = 1, O = Q;
-    __device__ static int in_off(int) { return 0; }
+    static constexpr int NCOL = D * D, C = D, NT = 1, O = Q, OUT = 0;
+    __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
-    __device__ static int out(int o, int n) { return n + NCOL * o; }
 };
 template <int D, int Q>
 struct MF2 {
-    static constexpr int NCOL = Q * D, C = D, NT = 1, O = Q;
-    __device__ static int in_off(int) { return 0; }
+    static constexpr int NCOL = Q * D, C = D, NT = 1, O = Q, OUT = 0;
+    __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
-    __device__ static int out(int o, int n) { return n + NCOL * o; }
 };
 template <int D, int Q>
 struct MF3 {
-    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = Q;
-    __device__ static int in_off(int) { return 0; }
+    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = Q, OUT = 0;
+    __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
-    __device__ static int out(int o, int n) { return n + NCOL * o; }
 };
 template <int D, int Q>
 struct MT1 {
-    static constexpr int NCOL = Q * Q, C = Q, NT = 1, O = D;
-    __device__ static int in_off(int) { return 0; }
+    static constexpr int NCOL = Q * Q, C = Q, NT = 1, O = D, OUT = 0;
+    __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
-    __device__ static int out(int o, int n) { return n + NCOL * o; }
 };
 template <int D, int Q>
 struct MT2 {
-    static constexpr int NCOL = Q * D, C = Q, NT = 1, O = D;
-    __device__ static int in_off(int) { return 0; }
+    static constexpr int NCOL = Q * D, C = Q, NT = 1, O = D, OUT = 0;
+    __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
-    __device__ static int out(int o, int n) { return n + NCOL * o; }
 };
 template <int D, int Q>
 struct MT3 {
-    static constexpr int NCOL = D * D, C = Q, NT = 1, O = D;
-    __device__ static int in_off(int) { return 0; }
+    static constexpr int NCOL = D * D, C = Q, NT = 1, O = D, OUT = 0;
+    __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
-    __device__ static int out(int o, int n) { return n + NCOL * o; }
 };
 
 }  // namespace hexpa

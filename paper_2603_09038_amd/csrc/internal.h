@@ -76,7 +76,7 @@ hipError_t launch_load(const pa_op *op, const double *fq, double *b, hipStream_t
 hipError_t launch_apply(const pa_op *op, int variant, const double *x, double *y,
                         const int32_t *elem_list, int nlist, hipStream_t s, bool *supported);
 hipError_t launch_diag(const pa_op *op, double *diag, hipStream_t s);
-hipError_t launch_debug_mfma(const double *A, const double *B, double *D, hipStream_t s);
+hipError_t launch_debug_mfma(int shape, const double *A, const double *B, double *D, hipStream_t s);
 // vector kernels (k_vec.hip)
 hipError_t vec_fill(double *y, double v, int64_t n, hipStream_t s);
 hipError_t vec_copy(double *y, const double *x, int64_t n, hipStream_t s);

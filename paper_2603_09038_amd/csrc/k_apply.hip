@@ -1,199 +1,289 @@
 // Fused PA apply kernels (mass, diffusion, mass+diffusion) and their launcher.
+//
+// Persistent workgroups: the grid holds about as many workgroups as the chip keeps
+// resident, and each one walks a strided list of element groups.  While group g is being
+// contracted, the DOF map and then the gathered x of group g+stride are already in flight
+// (and, with kPrefetchD, its quadrature data D), so HBM latency overlaps the LDS/MFMA work
+// of the current group instead of stalling every workgroup at its start.
+#include <type_traits>
+
 #include "apply_passes.h"
+
+#ifndef HEXPA_PREFETCH_D
+#define HEXPA_PREFETCH_D 0
+#endif
+#ifndef HEXPA_OVERSUB
+#define HEXPA_OVERSUB 1
+#endif
 
 namespace hexpa {
 
-// Element-group index of this workgroup.  Workgroups are dealt to the 8 XCDs round-robin
-// (block b runs on XCD b % 8); remapping gives every XCD one contiguous range of element
-// groups, so neighbouring elements (which share DOFs of x and y) meet in the same L2.
-__device__ __forceinline__ int xcd_group(int b, int ngroups)
+constexpr bool kPrefetchD = HEXPA_PREFETCH_D != 0;  // double-buffer D in registers across groups
+#ifndef HEXPA_LATE_D
+#define HEXPA_LATE_D 1
+#endif
+constexpr bool kLateD = HEXPA_LATE_D != 0;  // load D only at the D-step (no prefetch)
+constexpr int kOversub = HEXPA_OVERSUB;             // resident-workgroup multiples in the grid (0: one group each)
+#ifndef HEXPA_MIN_BLOCKS
+#define HEXPA_MIN_BLOCKS 3
+#endif
+constexpr int kMinBlocksPerCU = HEXPA_MIN_BLOCKS;   // register budget: workgroups resident per CU
+
+template <class S>
+struct GroupRegs {
+    static constexpr int NM = (S::E * S::D3 + kThreads - 1) / kThreads;  // map/x slots per thread
+};
+
+// D of group g into registers: slot s of thread tid is qp entry L = tid + s*256 of the group.
+template <class S>
+__device__ __forceinline__ void load_qdata(double (&dq)[S::NS][S::NCOMP], const double *__restrict__ qd,
+                                           const int32_t *__restrict__ elist, int e0, int nv, int tid)
 {
-    const int per = ngroups >> 3, rem = ngroups & 7;
-    const int x = b & 7, i = b >> 3;
-    return x * per + (x < rem ? x : rem) + i;
+#pragma unroll
+    for (int s = 0; s < S::NS; ++s) {
+        const int L = tid + s * kThreads;
+        const int e = L / S::Q3, r = L - e * S::Q3;
+        const bool ok = e < nv;
+        const int64_t ge = ok ? (elist ? elist[e0 + e] : e0 + e) : 0;
+        const double *src = qd + ge * (int64_t)(S::NCOMP * S::Q3) + r;
+#pragma unroll
+        for (int c = 0; c < S::NCOMP; ++c) dq[s][c] = ok ? __builtin_nontemporal_load(src + c * S::Q3) : 0.0;
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void load_map(int32_t (&m)[GroupRegs<S>::NM], const int32_t *__restrict__ emap,
+                                         const int32_t *__restrict__ elist, int e0, int nv, int tid)
+{
+#pragma unroll
+    for (int s = 0; s < GroupRegs<S>::NM; ++s) {
+        const int L = tid + s * kThreads;
+        const int e = L / S::D3, I = L - e * S::D3;
+        int32_t gi = -1;
+        if (e < nv) {
+            const int64_t ge = elist ? elist[e0 + e] : e0 + e;
+            gi = emap[ge * S::D3 + I];
+        }
+        m[s] = gi;
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void load_x(double (&xv)[GroupRegs<S>::NM], const int32_t (&m)[GroupRegs<S>::NM],
+                                       const double *__restrict__ x)
+{
+#pragma unroll
+    for (int s = 0; s < GroupRegs<S>::NM; ++s) xv[s] = m[s] >= 0 ? x[m[s]] : 0.0;
+}
+
+// One contraction pass with the chosen executor.  The MFMA A-operands are read from the
+// LDS copy of the tables right before the pass (short live ranges, no hoisting across the
+// barriers); the VALU executor reads the tables with uniform loads from global memory.
+template <class P, int E, bool MFMA, class Out>
+__device__ __forceinline__ void run_pass(const double *in, int szin, const DevTables *stab, const DevTables *gtab,
+                                         const Out &out, int tid)
+{
+    if constexpr (MFMA) {
+        double a[PassRegs<P>::RT][PassRegs<P>::KC];
+        load_a<P>(stab, a, tid & 63);
+        mfma_pass<P, E>(in, szin, a, out, __builtin_amdgcn_readfirstlane(tid >> 6), tid & 63);
+    } else {
+        valu_pass<P, E>(in, szin, gtab, out, tid);
+    }
 }
 
 template <int D, int Q, int OPS, bool MFMA, bool ATOMIC>
-__global__ __launch_bounds__(kThreads) void k_apply(int nelem, int ngroups, const int32_t *__restrict__ elist,
+__global__ __launch_bounds__(kThreads, kMinBlocksPerCU) void k_apply(int nelem, int ngroups, const int32_t *__restrict__ elist,
                                                     const int32_t *__restrict__ emap,
                                                     const double *__restrict__ qd,
                                                     const DevTables *__restrict__ tab,
                                                     const double *__restrict__ x, double *__restrict__ y)
 {
     using S = Shape<D, Q, OPS>;
-    constexpr int E = S::E, D3 = S::D3, Q3 = S::Q3, NS = S::NS, NC = S::NCOMP;
+    constexpr int E = S::E, D3 = S::D3, Q3 = S::Q3, NS = S::NS, NC = S::NCOMP, NM = GroupRegs<S>::NM;
     constexpr bool M = S::kMass;
-    __shared__ double bufA[E * S::SZ_A];
-    __shared__ double bufB[E * S::SZ_B];
+    __shared__ double bufA[E * S::SZ_A + S::SLACK];
+    __shared__ double bufB[E * S::SZ_B + S::SLACK];
     __shared__ int32_t lmap[E * D3];
+    __shared__ DevTables stab;  // 1-D tables in LDS: MFMA A-operands are re-read per pass
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g = xcd_group(blockIdx.x, ngroups);
-    const int e0 = g * E;
-    const int nv = min(E, nelem - e0);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += kThreads)
+        reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
 
-    // Quadrature data of the group, issued first so its HBM latency hides under the
-    // forward contractions: slot s of thread tid is qp entry L = tid + s*256 of the group.
+    // Workgroup b runs on XCD b % 8.  XCD x owns the contiguous group range
+    // [G x / 8, G (x+1) / 8) so neighbouring elements (sharing DOFs of x and y) meet in the
+    // same L2; its workgroups take that range's groups round-robin.
+    // (Grids of fewer than 8 workgroups just stride over all groups.)
+    const int nb = gridDim.x;
+    int g, gend, nbx;
+    if (nb >= 8) {
+        const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+        nbx = (nb >> 3) + (xcd < (nb & 7) ? 1 : 0);
+        gend = (int)(((int64_t)ngroups * (xcd + 1)) >> 3);
+        g = (int)(((int64_t)ngroups * xcd) >> 3) + slot;
+    } else {
+        nbx = nb;
+        gend = ngroups;
+        g = blockIdx.x;
+    }
+    if (g >= gend) return;
+
     double dq[NS][NC];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int L = tid + s * kThreads;
-        const int e = L / Q3, r = L - e * Q3;
-        const bool ok = e < nv;
-        const int64_t ge = ok ? (elist ? elist[e0 + e] : e0 + e) : 0;
-        const double *src = qd + ge * (int64_t)(NC * Q3) + r;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) dq[s][c] = ok ? __builtin_nontemporal_load(src + c * Q3) : 0.0;
+    int32_t mcur[NM];
+    double xcur[NM];
+    {
+        const int e0 = g * E, nv = min(E, nelem - e0);
+        if constexpr (!kLateD) load_qdata<S>(dq, qd, elist, e0, nv, tid);
+        load_map<S>(mcur, emap, elist, e0, nv, tid);
+        load_x<S>(xcur, mcur, x);
     }
 
-    // Gather x_E = G_e x into X[e][n=(j,k)][i] (= local node order) and keep the map.
-    for (int L = tid; L < E * D3; L += kThreads) {
-        const int e = L / D3, I = L - e * D3;
-        int32_t gi = -1;
-        double v = 0.0;
-        if (e < nv) {
-            const int64_t ge = elist ? elist[e0 + e] : e0 + e;
-            gi = emap[ge * D3 + I];
-            v = x[gi];
-        }
-        lmap[L] = gi;
-        bufA[e * S::SZ_A + I] = v;
-    }
+    for (;;) {
+        const int e0 = g * E, nv = min(E, nelem - e0);
+        const int gn = g + nbx;
+        const bool more = gn < gend;
+        const int e0n = gn * E, nvn = more ? min(E, nelem - e0n) : 0;
 
-    constexpr int RBF = (S::kDiff ? (2 * Q + 15) / 16 : (Q + 15) / 16);
-    __syncthreads();
-
-    if constexpr (S::kDiff) {
-        using F1 = DF1<D, Q, M>; using F2 = DF2<D, Q, M>; using F3 = DF3<D, Q, M>;
-        using T1a = DT1a<D, Q, M>; using T1b = DT1b<D, Q, M>;
-        using T2a = DT2a<D, Q, M>; using T2b = DT2b<D, Q, M>; using T3 = DT3<D, Q, M>;
-        if constexpr (MFMA) {
-            double aF[PassRegs<F1>::RB][PassRegs<F1>::KC];
-            load_a<F1>(tab, aF, lane);
-            mfma_pass<F1, E>(bufA, S::SZ_A, aF, LdsOut{bufB, S::SZ_B}, wave, lane);
-            __syncthreads();
-            mfma_pass<F2, E>(bufB, S::SZ_B, aF, LdsOut{bufA, S::SZ_A}, wave, lane);
-            __syncthreads();
-            mfma_pass<F3, E>(bufA, S::SZ_A, aF, LdsOut{bufB, S::SZ_B}, wave, lane);
-        } else {
-            valu_pass<F1, E>(bufA, S::SZ_A, tab, LdsOut{bufB, S::SZ_B}, tid);
-            __syncthreads();
-            valu_pass<F2, E>(bufB, S::SZ_B, tab, LdsOut{bufA, S::SZ_A}, tid);
-            __syncthreads();
-            valu_pass<F3, E>(bufA, S::SZ_A, tab, LdsOut{bufB, S::SZ_B}, tid);
+        // stage x_E = G_e x (local node order = X[e][n=(j,k)][i]) and the map
+#pragma unroll
+        for (int s = 0; s < NM; ++s) {
+            const int L = tid + s * kThreads;
+            if (L < E * D3) {
+                const int e = L / D3, I = L - e * D3;
+                lmap[L] = mcur[s];
+                bufA[e * S::SZ_A + I] = xcur[s];
+            }
         }
+        int32_t mnext[NM];
+        load_map<S>(mnext, emap, elist, e0n, nvn, tid);
+        double dnext[kPrefetchD ? NS : 1][NC];
+        if constexpr (kPrefetchD) load_qdata<S>(dnext, qd, elist, e0n, nvn, tid);
         __syncthreads();
-        // D at quadrature points: v = D grad_ref u (symmetric 3x3), v_u = D_m u.
+
+        // forward contractions
+        if constexpr (S::kDiff) {
+            run_pass<DF1<D, Q, M>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
+            __syncthreads();
+            run_pass<DF2a<D, Q, M>, E, MFMA>(bufB, S::SZ_B, &stab, tab, LdsOut{bufA, S::SZ_A}, tid);
+            run_pass<DF2b<D, Q, M>, E, MFMA>(bufB, S::SZ_B, &stab, tab, LdsOut{bufA, S::SZ_A}, tid);
+            __syncthreads();
+            run_pass<DF3a<D, Q, M>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
+            run_pass<DF3b<D, Q, M>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
+            run_pass<DF3c<D, Q, M>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
+        } else {
+            run_pass<MF1<D, Q>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
+            __syncthreads();
+            run_pass<MF2<D, Q>, E, MFMA>(bufB, S::SZ_B, &stab, tab, LdsOut{bufA, S::SZ_A}, tid);
+            __syncthreads();
+            run_pass<MF3<D, Q>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
+        }
+        // the next group's map has had the forward passes to arrive: start its x gather
+        double xnext[NM];
+        load_x<S>(xnext, mnext, x);
+        __syncthreads();
+
+        // D at quadrature points: v = D grad_ref u (symmetric 3x3) and/or v_u = D_m u
+        if constexpr (kLateD) load_qdata<S>(dq, qd, elist, e0, nv, tid);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int L = tid + s * kThreads;
             if (L < E * Q3) {
                 const int e = L / Q3, r = L - e * Q3;
                 double *V = bufB + e * S::SZ_B + r;
-                const double g0 = V[0], g1 = V[Q3], g2 = V[2 * Q3];
                 const double *Dm = dq[s];
-                V[0] = Dm[0] * g0 + Dm[1] * g1 + Dm[2] * g2;
-                V[Q3] = Dm[1] * g0 + Dm[3] * g1 + Dm[4] * g2;
-                V[2 * Q3] = Dm[2] * g0 + Dm[4] * g1 + Dm[5] * g2;
-                if constexpr (M) V[3 * Q3] = Dm[6] * V[3 * Q3];
+                if constexpr (S::kDiff) {
+                    using CH = Chan<Q, M>;
+                    const double g0 = V[CH::X], g1 = V[CH::Y], g2 = V[CH::Z];
+                    V[CH::X] = Dm[0] * g0 + Dm[1] * g1 + Dm[2] * g2;
+                    V[CH::Y] = Dm[1] * g0 + Dm[3] * g1 + Dm[4] * g2;
+                    V[CH::Z] = Dm[2] * g0 + Dm[4] * g1 + Dm[5] * g2;
+                    if constexpr (M) V[CH::V] = Dm[6] * V[CH::V];
+                } else {
+                    V[0] *= Dm[0];
+                }
             }
         }
-        __syncthreads();
-        if constexpr (MFMA) {
-            double aTG[PassRegs<T1a>::RB][PassRegs<T1a>::KC];
-            double aTB[PassRegs<T1b>::RB][PassRegs<T1b>::KC];
-            load_a<T1a>(tab, aTG, lane);
-            load_a<T1b>(tab, aTB, lane);
-            mfma_pass<T1a, E>(bufB, S::SZ_B, aTG, LdsOut{bufA, S::SZ_A}, wave, lane);
-            mfma_pass<T1b, E>(bufB, S::SZ_B, aTB, LdsOut{bufA, S::SZ_A}, wave, lane);
-            __syncthreads();
-            double a2[PassRegs<T2a>::RB][PassRegs<T2a>::KC];
-            load_a<T2a>(tab, a2, lane);
-            mfma_pass<T2a, E>(bufA, S::SZ_A, a2, LdsOut{bufB, S::SZ_B}, wave, lane);
-            mfma_pass<T2b, E>(bufA, S::SZ_A, aTB, LdsOut{bufB, S::SZ_B}, wave, lane);
-            __syncthreads();
-            double a3[PassRegs<T3>::RB][PassRegs<T3>::KC];
-            load_a<T3>(tab, a3, lane);
-            mfma_pass<T3, E>(bufB, S::SZ_B, a3, GlobalOut<ATOMIC>{y, lmap, D3}, wave, lane);
-        } else {
-            valu_pass<T1a, E>(bufB, S::SZ_B, tab, LdsOut{bufA, S::SZ_A}, tid);
-            valu_pass<T1b, E>(bufB, S::SZ_B, tab, LdsOut{bufA, S::SZ_A}, tid);
-            __syncthreads();
-            valu_pass<T2a, E>(bufA, S::SZ_A, tab, LdsOut{bufB, S::SZ_B}, tid);
-            valu_pass<T2b, E>(bufA, S::SZ_A, tab, LdsOut{bufB, S::SZ_B}, tid);
-            __syncthreads();
-            valu_pass<T3, E>(bufB, S::SZ_B, tab, GlobalOut<ATOMIC>{y, lmap, D3}, tid);
-        }
-    } else {
-        using F1 = MF1<D, Q>; using F2 = MF2<D, Q>; using F3 = MF3<D, Q>;
-        using T1 = MT1<D, Q>; using T2 = MT2<D, Q>; using T3 = MT3<D, Q>;
-        if constexpr (MFMA) {
-            double aF[PassRegs<F1>::RB][PassRegs<F1>::KC];
-            load_a<F1>(tab, aF, lane);
-            mfma_pass<F1, E>(bufA, S::SZ_A, aF, LdsOut{bufB, S::SZ_B}, wave, lane);
-            __syncthreads();
-            mfma_pass<F2, E>(bufB, S::SZ_B, aF, LdsOut{bufA, S::SZ_A}, wave, lane);
-            __syncthreads();
-            mfma_pass<F3, E>(bufA, S::SZ_A, aF, LdsOut{bufB, S::SZ_B}, wave, lane);
-        } else {
-            valu_pass<F1, E>(bufA, S::SZ_A, tab, LdsOut{bufB, S::SZ_B}, tid);
-            __syncthreads();
-            valu_pass<F2, E>(bufB, S::SZ_B, tab, LdsOut{bufA, S::SZ_A}, tid);
-            __syncthreads();
-            valu_pass<F3, E>(bufA, S::SZ_A, tab, LdsOut{bufB, S::SZ_B}, tid);
-        }
-        __syncthreads();
+        if (more && !kLateD) {
+            if constexpr (kPrefetchD) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int L = tid + s * kThreads;
-            if (L < E * Q3) {
-                const int e = L / Q3, r = L - e * Q3;
-                bufB[e * S::SZ_B + r] *= dq[s][0];
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) dq[s][c] = dnext[s][c];
+            } else {
+                load_qdata<S>(dq, qd, elist, e0n, nvn, tid);
             }
         }
         __syncthreads();
-        if constexpr (MFMA) {
-            double aT[PassRegs<T1>::RB][PassRegs<T1>::KC];
-            load_a<T1>(tab, aT, lane);
-            mfma_pass<T1, E>(bufB, S::SZ_B, aT, LdsOut{bufA, S::SZ_A}, wave, lane);
+
+        // transposed contractions and scatter-add
+        if constexpr (S::kDiff) {
+            using CH = Chan<Q, M>;
+            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, MFMA>(bufB, S::SZ_B, &stab, tab, LdsOut{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, MFMA>(bufB, S::SZ_B, &stab, tab, LdsOut{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, MFMA>(bufB, S::SZ_B, &stab, tab, LdsOut{bufA, S::SZ_A}, tid);
+            if constexpr (M)
+                run_pass<DT1<D, Q, M, CH::V, 3, false>, E, MFMA>(bufB, S::SZ_B, &stab, tab, LdsOut{bufA, S::SZ_A}, tid);
             __syncthreads();
-            mfma_pass<T2, E>(bufA, S::SZ_A, aT, LdsOut{bufB, S::SZ_B}, wave, lane);
+            run_pass<DT2a<D, Q, M>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
+            run_pass<DT2b<D, Q, M>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
             __syncthreads();
-            mfma_pass<T3, E>(bufB, S::SZ_B, aT, GlobalOut<ATOMIC>{y, lmap, D3}, wave, lane);
+            run_pass<DT3<D, Q, M>, E, MFMA>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC>{y, lmap, D3}, tid);
         } else {
-            valu_pass<T1, E>(bufB, S::SZ_B, tab, LdsOut{bufA, S::SZ_A}, tid);
+            run_pass<MT1<D, Q>, E, MFMA>(bufB, S::SZ_B, &stab, tab, LdsOut{bufA, S::SZ_A}, tid);
             __syncthreads();
-            valu_pass<T2, E>(bufA, S::SZ_A, tab, LdsOut{bufB, S::SZ_B}, tid);
+            run_pass<MT2<D, Q>, E, MFMA>(bufA, S::SZ_A, &stab, tab, LdsOut{bufB, S::SZ_B}, tid);
             __syncthreads();
-            valu_pass<T3, E>(bufB, S::SZ_B, tab, GlobalOut<ATOMIC>{y, lmap, D3}, tid);
+            run_pass<MT3<D, Q>, E, MFMA>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC>{y, lmap, D3}, tid);
+        }
+        if (!more) break;
+        __syncthreads();  // LDS (X, map) is rewritten by the next group
+        g = gn;
+#pragma unroll
+        for (int s = 0; s < NM; ++s) {
+            mcur[s] = mnext[s];
+            xcur[s] = xnext[s];
         }
     }
-    (void)RBF;
 }
 
 // ------------------------------------------------------------------ launcher
-template <int D, int Q, int OPS>
-static hipError_t launch_t(const pa_op *op, int variant, const double *x, double *y, const int32_t *elist, int n,
-                           hipStream_t s)
+template <int D, int Q, int OPS, bool MFMA, bool ATOMIC>
+static hipError_t launch_k(const pa_op *op, const double *x, double *y, const int32_t *elist, int n, hipStream_t s)
 {
     using S = Shape<D, Q, OPS>;
     const int ngroups = (n + S::E - 1) / S::E;
     if (ngroups == 0) return hipSuccess;
-    dim3 grid(ngroups), block(kThreads);
-    switch (variant) {
-    case PA_VARIANT_VALU:
-        hipLaunchKernelGGL((k_apply<D, Q, OPS, false, true>), grid, block, 0, s, n, ngroups, elist, op->d_elem_dofs,
-                           op->d_qdata, op->d_tab, x, y);
-        break;
-    case PA_VARIANT_MFMA_COLORED:
-        hipLaunchKernelGGL((k_apply<D, Q, OPS, true, false>), grid, block, 0, s, n, ngroups, elist, op->d_elem_dofs,
-                           op->d_qdata, op->d_tab, x, y);
-        break;
-    default:
-        hipLaunchKernelGGL((k_apply<D, Q, OPS, true, true>), grid, block, 0, s, n, ngroups, elist, op->d_elem_dofs,
-                           op->d_qdata, op->d_tab, x, y);
+    auto kern = k_apply<D, Q, OPS, MFMA, ATOMIC>;
+    int nblocks = ngroups;
+    if (kOversub > 0) {
+        // resident capacity of the device for this kernel (queried once)
+        static int cap = 0;
+        if (cap == 0) {
+            int per_cu = 0, dev = 0, ncu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+                ncu = 256;
+            cap = per_cu * ncu * kOversub;
+        }
+        nblocks = ngroups < cap ? ngroups : cap;
     }
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreads), 0, s, n, ngroups, elist, op->d_elem_dofs, op->d_qdata,
+                       op->d_tab, x, y);
     return hipGetLastError();
+}
+
+template <int D, int Q, int OPS>
+static hipError_t launch_t(const pa_op *op, int variant, const double *x, double *y, const int32_t *elist, int n,
+                           hipStream_t s)
+{
+    switch (variant) {
+    case PA_VARIANT_VALU: return launch_k<D, Q, OPS, false, true>(op, x, y, elist, n, s);
+    case PA_VARIANT_MFMA_COLORED: return launch_k<D, Q, OPS, true, false>(op, x, y, elist, n, s);
+    default: return launch_k<D, Q, OPS, true, true>(op, x, y, elist, n, s);
+    }
 }
 
 template <int P>

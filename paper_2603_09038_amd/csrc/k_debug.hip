@@ -1,7 +1,9 @@
-// One FP64 MFMA, for pinning the operand/lane layout the apply kernels rely on.
-// Operands: A-operand lane l = A[l % 16][l / 16], B-operand lane l = B[l / 16][l % 16].
-// The raw accumulator is written lane-major (Draw[4 l + v] = acc[v]) so the test can
-// read off which (row, col) of D = A B each lane/element holds.
+// One FP64 MFMA, for pinning the operand/lane layouts the apply kernels rely on.
+//  shape 16: v_mfma_f64_16x16x4f64, A-operand lane l = A[l % 16][l / 16], B-operand lane
+//            l = B[l / 16][l % 16]; raw accumulator written lane-major, Draw[4 l + v].
+//  shape 4:  v_mfma_f64_4x4x4f64 (4 blocks), block beta = (l >> 2) & 3 takes A-operand
+//            A[beta][l & 3][l >> 4] and B-operand B[beta][l >> 4][l & 3]; Draw[l] = result.
+// The tests read off which entry of the product each lane/element holds.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -22,11 +24,23 @@ __global__ __launch_bounds__(64) void k_debug_mfma(const double *__restrict__ A,
 #pragma unroll
     for (int v = 0; v < 4; ++v) Draw[4 * l + v] = acc[v];
 }
+
+__global__ __launch_bounds__(64) void k_debug_mfma4(const double *__restrict__ A, const double *__restrict__ B,
+                                                    double *__restrict__ Draw)
+{
+    const int l = threadIdx.x, beta = (l >> 2) & 3;
+    const double a = A[beta * 16 + (l & 3) * 4 + (l >> 4)];
+    const double b = B[beta * 16 + (l >> 4) * 4 + (l & 3)];
+    Draw[l] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, 0.0, 0, 0, 0);
+}
 }  // namespace
 
-hipError_t launch_debug_mfma(const double *A, const double *B, double *D, hipStream_t s)
+hipError_t launch_debug_mfma(int shape, const double *A, const double *B, double *D, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_debug_mfma, dim3(1), dim3(64), 0, s, A, B, D);
+    if (shape == 4)
+        hipLaunchKernelGGL(k_debug_mfma4, dim3(1), dim3(64), 0, s, A, B, D);
+    else
+        hipLaunchKernelGGL(k_debug_mfma, dim3(1), dim3(64), 0, s, A, B, D);
     return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ def _load():
         "pa_set_variant": [vp, i32],
         "pa_info": [vp, ctypes.POINTER(Info)],
         "cg_solve": [vp, vp, vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgResult), vp],
-        "pa_debug_mfma_f64": [vp, vp, vp, vp],
+        "pa_debug_mfma_f64": [i32, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -238,8 +238,8 @@ def cg_solve(h, b, x, rtol=1e-8, max_it=10000, mode=PA_CG_JACOBI, check_every=1,
             "rel_res_true": r.rel_res_true, "seconds": r.seconds}
 
 
-def pa_debug_mfma_f64(A, B, D, stream=None):
-    _check(_lib.pa_debug_mfma_f64(_dptr(A), _dptr(B), _dptr(D), _stream(stream)))
+def pa_debug_mfma_f64(shape, A, B, D, stream=None):
+    _check(_lib.pa_debug_mfma_f64(int(shape), _dptr(A), _dptr(B), _dptr(D), _stream(stream)))
 
 
 # ------------------------------------------------------------------ convenience

@@ -37,9 +37,40 @@ def _ops_o(ops):
     return (oracle.MASS if ops & 1 else 0) | (oracle.DIFFUSION if ops & 2 else 0)
 
 
-def test_mfma_f64_lane_layout(hx):
-    """One v_mfma_f64_16x16x4f64 against a CPU GEMM: pins the operand/result lane maps the
-    kernels assume (lane l, element v holds D[l/16 + 4v][l%16])."""
+def test_mfma_f64_4x4x4_lane_layout(hx):
+    """v_mfma_f64_4x4x4f64 (the apply kernels' MFMA): block b = (l>>2)&3 reads A[b][l&3][l>>4],
+    B[b][l>>4][l&3] and lane l returns D[b][l>>4][l&3] — pinned with operands that make every
+    product entry distinct, then with random operands against a CPU product."""
+    import torch
+    raw = torch.zeros(64, dtype=torch.float64, device="cuda")
+    # D[b][i][j] = j + 10 i + 100 b + 1000 (via k = 0 and k = 1 terms)
+    A = np.zeros((4, 4, 4))
+    B = np.zeros((4, 4, 4))
+    for b in range(4):
+        A[b, :, 0] = 1.0
+        A[b, :, 1] = np.arange(4)
+        B[b, 0, :] = np.arange(4) + 100 * b + 1000
+        B[b, 1, :] = 10.0
+    hx.pa_debug_mfma_f64(4, _cuda(A.ravel()), _cuda(B.ravel()), raw)
+    raw = raw.cpu().numpy()
+    lanes = np.arange(64)
+    expect = (lanes & 3) + 10 * (lanes >> 4) + 100 * ((lanes >> 2) & 3) + 1000
+    assert np.array_equal(raw, expect.astype(float)), raw.reshape(4, 16)
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((4, 4, 4))
+    B = rng.standard_normal((4, 4, 4))
+    hx.pa_debug_mfma_f64(4, _cuda(A.ravel()), _cuda(B.ravel()), raw := torch.zeros(64, dtype=torch.float64,
+                                                                                  device="cuda"))
+    raw = raw.cpu().numpy()
+    D = np.einsum("bik,bkj->bij", A, B)
+    got = np.zeros((4, 4, 4))
+    for l in range(64):
+        got[(l >> 2) & 3, l >> 4, l & 3] = raw[l]
+    np.testing.assert_allclose(got, D, rtol=1e-14, atol=1e-14)
+
+
+def test_mfma_f64_16x16x4_lane_layout(hx):
+    """v_mfma_f64_16x16x4f64 against a CPU GEMM: lane l, element v holds D[l/16 + 4v][l%16]."""
     import torch
     # structured operands: D[i][j] = j + 1000 i identifies every entry
     A = np.zeros((16, 4))
@@ -47,7 +78,7 @@ def test_mfma_f64_lane_layout(hx):
     B = np.zeros((4, 16))
     B[0, :], B[1, :] = np.arange(16), 1000.0
     raw = torch.zeros(256, dtype=torch.float64, device="cuda")
-    hx.pa_debug_mfma_f64(_cuda(A.ravel()), _cuda(B.ravel()), raw)
+    hx.pa_debug_mfma_f64(16, _cuda(A.ravel()), _cuda(B.ravel()), raw)
     raw = raw.cpu().numpy().reshape(64, 4)
     held = {(int(v) // 1000, int(v) % 1000) for v in raw.ravel()}
     assert len(held) == 256  # every entry of D exactly once
@@ -60,7 +91,7 @@ def test_mfma_f64_lane_layout(hx):
     rng = np.random.default_rng(3)
     A = rng.standard_normal((16, 4))
     B = rng.standard_normal((4, 16))
-    hx.pa_debug_mfma_f64(_cuda(A.ravel()), _cuda(B.ravel()), raw := torch.zeros(256, dtype=torch.float64,
+    hx.pa_debug_mfma_f64(16, _cuda(A.ravel()), _cuda(B.ravel()), raw := torch.zeros(256, dtype=torch.float64,
                                                                                  device="cuda"))
     raw = raw.cpu().numpy().reshape(64, 4)
     D = np.zeros((16, 16))
