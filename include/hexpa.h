@@ -113,6 +113,17 @@ int pa_apply(pa_op *op, const double *x, double *y, void *stream);
    x and y must not alias.  Asynchronous. */
 int pa_apply_add(pa_op *op, const double *x, double *y, void *stream);
 
+/* Mixed-precision apply, y = A x (unconstrained), for the inner solver of iterative
+   refinement: x and y are device FP32 vectors [ndof]; the quadrature data is an FP32 copy
+   of D (rounded once from FP64, made on first use); the element tiles and every
+   intermediate of the sum-factorised contractions are rounded to FP16 (fmt = PA_LP_FP16)
+   or BF16 (PA_LP_BF16) as they enter v_mfma_f32_16x16x16{f16,bf16}, which accumulates in
+   FP32.  FP16 needs |x| well inside its range: callers scale x by a power of two.
+   y is overwritten.  Asynchronous. */
+#define PA_LP_FP16 0
+#define PA_LP_BF16 1
+int pa_apply_lp(pa_op *op, const float *x, float *y, int fmt, void *stream);
+
 /* y = A_c x with A_c = (I - E) A (I - E) + E, E = indicator of the essential DOFs.
    Uses handle-owned scratch; calls on one handle must not overlap.  Asynchronous. */
 int pa_apply_constrained(pa_op *op, const double *x, double *y, void *stream);
@@ -147,24 +158,34 @@ const char *pa_last_error(void);
 /* ------------------------------------------------------------------ solver */
 #define PA_CG_PLAIN 0      /* CG, no preconditioner */
 #define PA_CG_JACOBI 1     /* Jacobi-preconditioned CG, M = diag(A_c) */
+#define PA_CG_MIXED_IR 2   /* FP64 iterative refinement around an inner Jacobi-PCG that runs
+                              in FP32 vectors with the 16-bit-MFMA apply (pa_apply_lp) */
 
 typedef struct {
-    double rtol;         /* stop when ||r_k||_2 <= rtol ||b||_2 (recursive residual) */
-    int32_t max_it;
+    double rtol;         /* stop when ||r_k||_2 <= rtol ||b||_2 (recursive residual; for
+                            MIXED_IR the FP64 residual recomputed every outer step) */
+    int32_t max_it;      /* iterations (MIXED_IR: outer refinement steps) */
     int32_t mode;        /* PA_CG_* */
     int32_t check_every; /* read the residual norm back to the host every k iterations (>=1) */
-    int32_t constrained; /* 1: solve with A_c (b must vanish on essential DOFs) */
+    int32_t constrained; /* 1: solve with A_c; the essential entries of x are set to b's */
+    int32_t lp_fmt;      /* MIXED_IR: PA_LP_FP16 or PA_LP_BF16 */
+    int32_t inner_max;   /* MIXED_IR: inner iterations per refinement step */
+    double inner_rtol;   /* MIXED_IR: inner relative tolerance per refinement step */
 } pa_cg_opts;
 
 typedef struct {
     int32_t iters, status;
-    double rel_res_recursive; /* ||r_k|| / ||b|| of the recursion at exit */
+    double rel_res_recursive; /* ||r_k|| / ||b|| at exit (recursion; MIXED_IR: FP64 residual) */
     double rel_res_true;      /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
     double seconds;           /* wall time of the iteration (excludes diag and setup) */
+    int32_t inner_iters_total; /* MIXED_IR: inner PCG iterations over all refinement steps */
+    int32_t pad;
 } pa_cg_result;
 
 /* Solve A x = b (or A_c x = b) by (preconditioned) CG (Saad, Alg. 9.1), all vector work
-   and reductions in FP64 on the device.  x is the initial guess on entry and the
+   and reductions in FP64 on the device; or, with PA_CG_MIXED_IR, by iterative refinement:
+   r = b - A x in FP64, an inner Jacobi-PCG on the scaled residual in FP32 vectors with
+   pa_apply_lp and FP64 dot products, x += correction in FP64.  x is the initial guess on entry and the
    solution on exit.  Synchronous on `stream`.  Returns PA_OK, PA_ERR_NOT_CONVERGED
    (x holds the last iterate) or PA_ERR_BREAKDOWN. */
 int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
@@ -181,6 +202,13 @@ int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
              b = (l>>2)&3; writes Draw[l] (64 doubles).
    Returns PA_ERR_ARG for another shape. */
 int pa_debug_mfma_f64(int shape, const double *A, const double *B, double *D, void *stream);
+
+/* One v_mfma_f32_16x16x16f16 (bf16 = 0) or v_mfma_f32_16x16x16bf16_1k (bf16 != 0) on the
+   device, with A[16][16], B[16][16] FP32 row-major device arrays rounded to the 16-bit
+   format as they are loaded (round to nearest even); lane l supplies A[l%16][4(l/16)+t] and
+   B[4(l/16)+t][l%16], t = 0..3.  Writes the raw FP32 accumulator Draw[4*l + v] (256 floats):
+   the layout the mixed-precision apply assumes is Draw[4l+v] = (A B)[4(l/16)+v][l%16]. */
+int pa_debug_mfma16(int bf16, const float *A, const float *B, float *D, void *stream);
 
 #ifdef __cplusplus
 }

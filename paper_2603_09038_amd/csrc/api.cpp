@@ -41,6 +41,31 @@ hipError_t launch_apply(const pa_op *op, int variant, const double *x, double *y
     return hipSuccess;
 }
 
+hipError_t launch_apply_lp_p1(const pa_op *, int, const float *, float *, hipStream_t, bool *);
+hipError_t launch_apply_lp_p2(const pa_op *, int, const float *, float *, hipStream_t, bool *);
+hipError_t launch_apply_lp_p3(const pa_op *, int, const float *, float *, hipStream_t, bool *);
+hipError_t launch_apply_lp_p4(const pa_op *, int, const float *, float *, hipStream_t, bool *);
+hipError_t launch_apply_lp_p5(const pa_op *, int, const float *, float *, hipStream_t, bool *);
+hipError_t launch_apply_lp_p6(const pa_op *, int, const float *, float *, hipStream_t, bool *);
+hipError_t launch_apply_lp_p7(const pa_op *, int, const float *, float *, hipStream_t, bool *);
+hipError_t launch_apply_lp_p8(const pa_op *, int, const float *, float *, hipStream_t, bool *);
+
+hipError_t launch_apply_lp(const pa_op *op, int fmt, const float *x, float *y, hipStream_t s, bool *ok)
+{
+    switch (op->p) {
+    case 1: return launch_apply_lp_p1(op, fmt, x, y, s, ok);
+    case 2: return launch_apply_lp_p2(op, fmt, x, y, s, ok);
+    case 3: return launch_apply_lp_p3(op, fmt, x, y, s, ok);
+    case 4: return launch_apply_lp_p4(op, fmt, x, y, s, ok);
+    case 5: return launch_apply_lp_p5(op, fmt, x, y, s, ok);
+    case 6: return launch_apply_lp_p6(op, fmt, x, y, s, ok);
+    case 7: return launch_apply_lp_p7(op, fmt, x, y, s, ok);
+    case 8: return launch_apply_lp_p8(op, fmt, x, y, s, ok);
+    }
+    *ok = false;
+    return hipSuccess;
+}
+
 }  // namespace hexpa
 
 using namespace hexpa;
@@ -92,6 +117,7 @@ extern "C" void pa_destroy(pa_op *op)
     if (!op) return;
     dfree(op->d_elem_dofs);
     dfree(op->d_qdata);
+    dfree(op->d_qdata32);
     dfree(op->d_vert);
     dfree(op->d_hex);
     dfree(op->d_tab);
@@ -416,96 +442,97 @@ extern "C" int pa_debug_mfma_f64(int shape, const double *A, const double *B, do
     return PA_OK;
 }
 
+extern "C" int pa_debug_mfma16(int bf16, const float *A, const float *B, float *D, void *stream)
+{
+    if (!A || !B || !D) return arg_error("pa_debug_mfma16: NULL argument");
+    HIP_OK(launch_debug_mfma16(bf16 ? 1 : 0, A, B, D, as_stream(stream)));
+    return PA_OK;
+}
+
+// ------------------------------------------------------------------ mixed-precision apply
+static int ensure_qdata32(pa_op *op, hipStream_t s)
+{
+    if (op->d_qdata32) return PA_OK;
+    const int64_t n = (int64_t)op->nelem * op->ncomp * op->q * op->q * op->q;
+    HIP_OK(dalloc(&op->d_qdata32, (size_t)n));
+    HIP_OK(vec_to_f32(op->d_qdata32, op->d_qdata, 1.0, n, s));
+    return PA_OK;
+}
+
+static int do_apply_lp(pa_op *op, const float *x, float *y, int fmt, hipStream_t s)
+{
+    int rc = ensure_qdata32(op, s);
+    if (rc) return rc;
+    bool ok = true;
+    HIP_OK(vec_fill(y, 0.0f, op->ndof, s));
+    HIP_OK(launch_apply_lp(op, fmt, x, y, s, &ok));
+    if (!ok) {
+        set_error("mixed-precision apply not instantiated for this (p, q1d, ops)");
+        return PA_ERR_UNSUPPORTED;
+    }
+    return PA_OK;
+}
+
+extern "C" int pa_apply_lp(pa_op *op, const float *x, float *y, int fmt, void *stream)
+{
+    PA_TRY
+    if (!op || !x || !y) return arg_error("pa_apply_lp: NULL argument");
+    if ((const void *)x == (const void *)y) return arg_error("pa_apply_lp: x and y must not alias");
+    if (fmt != PA_LP_FP16 && fmt != PA_LP_BF16) return arg_error("pa_apply_lp: fmt must be PA_LP_FP16 or PA_LP_BF16");
+    return do_apply_lp(op, x, y, fmt, as_stream(stream));
+    PA_CATCH
+}
+
 // ------------------------------------------------------------------ CG
 namespace {
-struct CgWork {
-    double *r = nullptr, *p = nullptr, *Ap = nullptr, *dinv = nullptr, *partial = nullptr, *hist = nullptr,
-           *tmp = nullptr;
+// Device buffers of one (P)CG run in vector type T; sums and scalars are FP64.
+template <class T>
+struct PcgWork {
+    T *r = nullptr, *p = nullptr, *Ap = nullptr;
+    double *partial = nullptr, *hist = nullptr, *tmp = nullptr;
     CgScalars *sc = nullptr;
-    double *h_hist = nullptr;  // pinned
+    double *h_hist = nullptr;  // pinned: 2 slots x (r.r, breakdown)
     hipEvent_t ev[2] = {nullptr, nullptr};
-    ~CgWork()
+    int max_it = 0;
+    hipError_t init(int64_t n, int max_it_)
     {
-        dfree(r); dfree(p); dfree(Ap); dfree(dinv); dfree(partial); dfree(hist); dfree(tmp);
-        dfree(sc);
+        max_it = max_it_;
+        hipError_t e;
+        if ((e = dalloc(&r, n)) || (e = dalloc(&p, n)) || (e = dalloc(&Ap, n)) || (e = dalloc(&partial, 2 * kRedBlocks)) ||
+            (e = dalloc(&hist, 2 * ((size_t)max_it + 2))) || (e = dalloc(&tmp, 4)) || (e = dalloc(&sc, 1)))
+            return e;
+        if ((e = hipHostMalloc((void **)&h_hist, 4 * sizeof(double), hipHostMallocDefault))) return e;
+        if ((e = hipEventCreateWithFlags(&ev[0], hipEventDisableTiming))) return e;
+        return hipEventCreateWithFlags(&ev[1], hipEventDisableTiming);
+    }
+    ~PcgWork()
+    {
+        dfree(r); dfree(p); dfree(Ap); dfree(partial); dfree(hist); dfree(tmp); dfree(sc);
         if (h_hist) (void)hipHostFree(h_hist);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
     }
 };
-}  // namespace
 
-// y = A p with p vanishing on the essential DOFs (CG invariant): A_c p = A p outside, 0 on them.
-static int cg_apply(pa_op *op, bool constrained, const double *p, double *y, hipStream_t s)
+// (P)CG iterations from an initialised state (r, p, scalars, hist[0] = r0.r0 read back as
+// rr0).  Stops when r.r <= tol2, on breakdown, or after max_it.  The host inspects the
+// residual of the previous check while the next iteration is already queued, so the
+// device never idles waiting for the host.
+template <class T, class ApplyF>
+int pcg_iterate(ApplyF apply, T *x, const T *dinv, int64_t n, double tol2, int max_it, int check, PcgWork<T> &w,
+                hipStream_t s, double rr0, int *iters, double *rr_out)
 {
-    int rc = do_apply(op, op->variant, p, y, s);
-    if (rc) return rc;
-    if (constrained && op->ness) HIP_OK(vec_zero_list(y, op->d_ess, op->ness, s));
-    return PA_OK;
-}
-
-extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res, void *stream)
-{
-    PA_TRY
-    if (!op || !b || !x || !o || !res) return arg_error("cg_solve: NULL argument");
-    if (!(o->rtol > 0.0) || o->max_it < 1) return arg_error("cg_solve: need rtol > 0 and max_it >= 1");
-    if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI) return arg_error("cg_solve: unknown mode");
-    std::memset(res, 0, sizeof(*res));
-    hipStream_t s = as_stream(stream);
-    const int64_t n = op->ndof;
-    const bool con = o->constrained != 0;
-    const int check = o->check_every < 1 ? 1 : o->check_every;
-    CgWork w;
-    HIP_OK(dalloc(&w.r, n));
-    HIP_OK(dalloc(&w.p, n));
-    HIP_OK(dalloc(&w.Ap, n));
-    HIP_OK(dalloc(&w.partial, 2 * kRedBlocks));
-    HIP_OK(dalloc(&w.hist, 2 * ((size_t)o->max_it + 2)));
-    HIP_OK(dalloc(&w.tmp, 4));
-    HIP_OK(dalloc(&w.sc, 1));
-    HIP_OK(hipHostMalloc((void **)&w.h_hist, 4 * sizeof(double), hipHostMallocDefault));
-    HIP_OK(hipEventCreateWithFlags(&w.ev[0], hipEventDisableTiming));
-    HIP_OK(hipEventCreateWithFlags(&w.ev[1], hipEventDisableTiming));
-    if (o->mode == PA_CG_JACOBI) {
-        HIP_OK(dalloc(&w.dinv, n));
-        int rc = pa_diag(op, w.dinv, con ? 1 : 0, s);
-        if (rc) return rc;
-        HIP_OK(vec_recip(w.dinv, w.dinv, n, s));
-    }
-    if (con && op->ness) HIP_OK(vec_copy_list(x, b, op->d_ess, op->ness, s));
-    // ||b||
-    HIP_OK(vec_dot(b, b, n, w.partial, w.tmp, s));
-    double bb = 0.0;
-    HIP_OK(hipMemcpyAsync(&bb, w.tmp, sizeof(double), hipMemcpyDeviceToHost, s));
-    // r = b - A x, p = M^{-1} r
-    int rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);
-    if (rc) return rc;
-    HIP_OK(cg_init(b, w.r, w.p, w.dinv, n, w.partial, w.sc, w.hist, s));
-    HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    const double bnorm = std::sqrt(bb);
-    if (bnorm == 0.0) {
-        HIP_OK(vec_fill(x, 0.0, n, s));
-        HIP_OK(hipStreamSynchronize(s));
-        res->status = PA_OK;
-        return PA_OK;
-    }
-    const double tol2 = (o->rtol * bnorm) * (o->rtol * bnorm);
-    double rr = w.h_hist[0];
+    double rr = rr0;
     int it = 0, status = PA_ERR_NOT_CONVERGED;
-    auto t0 = std::chrono::steady_clock::now();
     if (rr <= tol2) status = PA_OK;
-    int pending = -1;  // slot of the residual copy in flight (-1: none)
-    int nchecks = 0;
-    while (status == PA_ERR_NOT_CONVERGED && it < o->max_it) {
+    int pending = -1, nchecks = 0;
+    while (status == PA_ERR_NOT_CONVERGED && it < max_it) {
         ++it;
-        rc = cg_apply(op, con, w.p, w.Ap, s);
+        int rc = apply(w.p, w.Ap);
         if (rc) return rc;
-        HIP_OK(cg_alpha(w.p, w.Ap, n, w.partial, w.sc, s));
-        HIP_OK(cg_update(x, w.r, w.p, w.Ap, w.dinv, n, w.partial, w.sc, w.hist, it, s));
-        if (it % check == 0 || it == o->max_it) {
-            // lagged check: the host inspects the previous check's copy while this
-            // iteration is already queued, so the device never waits for the host
+        HIP_OK(cg_alpha<T>(w.p, w.Ap, n, w.partial, w.sc, s));
+        HIP_OK(cg_update<T>(x, w.r, w.p, w.Ap, dinv, n, w.partial, w.sc, w.hist, it, s));
+        if (it % check == 0 || it == max_it) {
             const int slot = (nchecks++) & 1;
             HIP_OK(hipMemcpyAsync(w.h_hist + 2 * slot, w.hist + 2 * (size_t)it, 2 * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
@@ -521,22 +548,176 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     }
     HIP_OK(hipStreamSynchronize(s));
     if (pending >= 0) {
-        const int ps = pending;
-        rr = w.h_hist[2 * ps];
-        if (w.h_hist[2 * ps + 1] != 0.0) status = PA_ERR_BREAKDOWN;
+        rr = w.h_hist[2 * pending];
+        if (w.h_hist[2 * pending + 1] != 0.0) status = PA_ERR_BREAKDOWN;
         else if (rr <= tol2) status = PA_OK;
     }
+    *iters = it;
+    *rr_out = rr;
+    return status;
+}
+}  // namespace
+
+// y = A p with p vanishing on the essential DOFs (CG invariant): A_c p = A p outside, 0 on them.
+static int cg_apply(pa_op *op, bool constrained, const double *p, double *y, hipStream_t s)
+{
+    int rc = do_apply(op, op->variant, p, y, s);
+    if (rc) return rc;
+    if (constrained && op->ness) HIP_OK(vec_zero_list(y, op->d_ess, op->ness, s));
+    return PA_OK;
+}
+
+static int true_residual(pa_op *op, bool con, const double *b, const double *x, double *tmp, double *tmp2,
+                         PcgWork<double> &w, double bnorm, hipStream_t s, double *rel)
+{
+    int rc = con ? do_apply_constrained(op, x, tmp, s) : do_apply(op, op->variant, x, tmp, s);
+    if (rc) return rc;
+    HIP_OK(cg_init<double>(b, tmp, tmp2, nullptr, op->ndof, w.partial, w.sc, w.hist, s));
+    HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    *rel = std::sqrt(w.h_hist[0]) / bnorm;
+    return PA_OK;
+}
+
+static int solve_mixed_ir(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res,
+                          hipStream_t s, double bnorm, PcgWork<double> &w64, const double *dinv64)
+{
+    const int64_t n = op->ndof;
+    const bool con = o->constrained != 0;
+    const int fmt = o->lp_fmt;
+    if (fmt != PA_LP_FP16 && fmt != PA_LP_BF16) return arg_error("cg_solve: lp_fmt must be PA_LP_FP16 or PA_LP_BF16");
+    const int inner_max = o->inner_max > 0 ? o->inner_max : 200;
+    const double inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-2;
+    const int check = o->check_every < 1 ? 1 : o->check_every;
+    int rc = ensure_qdata32(op, s);
+    if (rc) return rc;
+    PcgWork<float> w32;
+    HIP_OK(w32.init(n, inner_max));
+    float *d32 = nullptr, *dinv32 = nullptr;
+    HIP_OK(dalloc(&d32, n));
+    std::unique_ptr<void, void (*)(void *)> g1(d32, dfree);
+    if (dinv64) {
+        HIP_OK(dalloc(&dinv32, n));
+        HIP_OK(vec_to_f32(dinv32, dinv64, 1.0, n, s));
+    }
+    std::unique_ptr<void, void (*)(void *)> g2(dinv32, dfree);
+    auto apply32 = [&](const float *p, float *y) -> int {
+        int r2 = do_apply_lp(op, p, y, fmt, s);
+        if (r2) return r2;
+        if (con && op->ness) HIP_OK(vec_set_list(y, 0.0f, op->d_ess, op->ness, s));
+        return PA_OK;
+    };
+    auto t0 = std::chrono::steady_clock::now();
+    int status = PA_ERR_NOT_CONVERGED, outer = 0, inner_total = 0;
+    double rel = 0.0;
+    for (;;) {
+        // FP64 residual r = b - A x and its norm / max-abs scale
+        rc = con ? do_apply_constrained(op, x, w64.Ap, s) : do_apply(op, op->variant, x, w64.Ap, s);
+        if (rc) return rc;
+        HIP_OK(cg_init<double>(b, w64.Ap, w64.r, nullptr, n, w64.partial, w64.sc, w64.hist, s));  // Ap <- b - Ax
+        HIP_OK(vec_maxabs(w64.Ap, n, w64.partial, w64.tmp, s));
+        HIP_OK(hipMemcpyAsync(w64.h_hist, w64.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(w64.h_hist + 1, w64.tmp, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        rel = std::sqrt(w64.h_hist[0]) / bnorm;
+        const double rmax = w64.h_hist[1];
+        if (!std::isfinite(rel)) { status = PA_ERR_BREAKDOWN; break; }
+        if (rel <= o->rtol) { status = PA_OK; break; }
+        if (outer >= o->max_it) break;
+        ++outer;
+        // scale the residual by a power of two so its largest entry is in [0.5, 1)
+        int ex = 0;
+        std::frexp(rmax, &ex);
+        const double scale = std::ldexp(1.0, -ex);
+        HIP_OK(vec_to_f32(w32.r, w64.Ap, scale, n, s));
+        HIP_OK(vec_fill(d32, 0.0f, n, s));
+        HIP_OK(cg_init<float>(nullptr, w32.r, w32.p, dinv32, n, w32.partial, w32.sc, w32.hist, s));
+        HIP_OK(hipMemcpyAsync(w32.h_hist, w32.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        const double rr0 = w32.h_hist[0];
+        int it_in = 0;
+        double rr_in = 0.0;
+        int st = pcg_iterate<float>(apply32, d32, dinv32, n, inner_rtol * inner_rtol * rr0, inner_max, check, w32, s,
+                                    rr0, &it_in, &rr_in);
+        inner_total += it_in;
+        if (st == PA_ERR_BREAKDOWN && it_in <= 1) { status = PA_ERR_BREAKDOWN; break; }
+        if (st != PA_OK && st != PA_ERR_NOT_CONVERGED && st != PA_ERR_BREAKDOWN) return st;
+        HIP_OK(vec_axpy_f32(x, 1.0 / scale, d32, n, s));
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    res->seconds = std::chrono::duration<double>(t1 - t0).count();
+    res->iters = outer;
+    res->inner_iters_total = inner_total;
+    res->rel_res_recursive = rel;
+    double trel = 0.0;
+    rc = true_residual(op, con, b, x, w64.Ap, w64.r, w64, bnorm, s, &trel);
+    if (rc) return rc;
+    res->rel_res_true = trel;
+    res->status = status;
+    if (status == PA_ERR_NOT_CONVERGED) set_error("cg_solve: max_it refinement steps reached before rtol");
+    if (status == PA_ERR_BREAKDOWN) set_error("cg_solve: breakdown in mixed-precision refinement");
+    return status;
+}
+
+extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res, void *stream)
+{
+    PA_TRY
+    if (!op || !b || !x || !o || !res) return arg_error("cg_solve: NULL argument");
+    if (!(o->rtol > 0.0) || o->max_it < 1) return arg_error("cg_solve: need rtol > 0 and max_it >= 1");
+    if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI && o->mode != PA_CG_MIXED_IR)
+        return arg_error("cg_solve: unknown mode");
+    std::memset(res, 0, sizeof(*res));
+    hipStream_t s = as_stream(stream);
+    const int64_t n = op->ndof;
+    const bool con = o->constrained != 0;
+    const int check = o->check_every < 1 ? 1 : o->check_every;
+    PcgWork<double> w;
+    HIP_OK(w.init(n, o->mode == PA_CG_MIXED_IR ? 4 : o->max_it));
+    double *dinv = nullptr;
+    std::unique_ptr<void, void (*)(void *)> gd(nullptr, dfree);
+    if (o->mode != PA_CG_PLAIN) {  // Jacobi (also the inner preconditioner of MIXED_IR)
+        HIP_OK(dalloc(&dinv, n));
+        gd.reset(dinv);
+        int rc = pa_diag(op, dinv, con ? 1 : 0, s);
+        if (rc) return rc;
+        HIP_OK(vec_recip(dinv, dinv, n, s));
+    }
+    if (con && op->ness) HIP_OK(vec_copy_list(x, b, op->d_ess, op->ness, s));
+    HIP_OK(vec_dot<double>(b, b, n, w.partial, w.tmp, s));
+    double bb = 0.0;
+    HIP_OK(hipMemcpyAsync(&bb, w.tmp, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(bb);
+    if (bnorm == 0.0) {
+        HIP_OK(vec_fill(x, 0.0, n, s));
+        HIP_OK(hipStreamSynchronize(s));
+        res->status = PA_OK;
+        return PA_OK;
+    }
+    if (o->mode == PA_CG_MIXED_IR) return solve_mixed_ir(op, b, x, o, res, s, bnorm, w, dinv);
+
+    // r = b - A x, p = M^{-1} r
+    int rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);
+    if (rc) return rc;
+    HIP_OK(cg_init<double>(b, w.r, w.p, dinv, n, w.partial, w.sc, w.hist, s));
+    HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double tol2 = (o->rtol * bnorm) * (o->rtol * bnorm);
+    auto t0 = std::chrono::steady_clock::now();
+    int it = 0;
+    double rr = 0.0;
+    auto apply64 = [&](const double *p, double *y) { return cg_apply(op, con, p, y, s); };
+    const int status = pcg_iterate<double>(apply64, x, dinv, n, tol2, o->max_it, check, w, s, w.h_hist[0], &it, &rr);
+    if (status != PA_OK && status != PA_ERR_NOT_CONVERGED && status != PA_ERR_BREAKDOWN) return status;
     auto t1 = std::chrono::steady_clock::now();
     res->seconds = std::chrono::duration<double>(t1 - t0).count();
     res->iters = it;
     res->rel_res_recursive = std::sqrt(rr) / bnorm;
-    // true residual in FP64
-    rc = con ? do_apply_constrained(op, x, w.Ap, s) : do_apply(op, op->variant, x, w.Ap, s);
+    double trel = 0.0;
+    rc = true_residual(op, con, b, x, w.Ap, w.r, w, bnorm, s, &trel);
     if (rc) return rc;
-    HIP_OK(cg_init(b, w.Ap, w.r, nullptr, n, w.partial, w.sc, w.hist, s));
-    HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-    res->rel_res_true = std::sqrt(w.h_hist[0]) / bnorm;
+    res->rel_res_true = trel;
     res->status = status;
     if (status == PA_ERR_NOT_CONVERGED) set_error("cg_solve: max_it reached before rtol");
     if (status == PA_ERR_BREAKDOWN) set_error("cg_solve: breakdown (p^T A p <= 0 or non-finite scalar)");

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -57,7 +58,7 @@ constexpr int cmax3(int a, int b, int c) { return cmax(a, cmax(b, c)); }
 constexpr int cclamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // ------------------------------------------------------------------ element-group shape
-template <int D, int Q, int OPS>
+template <int D, int Q, int OPS, int TB = 8>  // TB: bytes of the LDS/vector scalar type
 struct Shape {
     static constexpr bool kMass = (OPS & 1) != 0;
     static constexpr bool kDiff = (OPS & 2) != 0;
@@ -74,7 +75,7 @@ struct Shape {
     static constexpr int SZ_A = cmax3(SZ_X, SZ_U2, SZ_W) | 1;
     static constexpr int SZ_B = cmax3(SZ_U1, SZ_G3, SZ_T) | 1;
     static constexpr int SLACK = 16 * 2 * kMaxQ;  // tail of each buffer for padded tile columns
-    static constexpr int PER_ELEM_BYTES = 8 * (SZ_A + SZ_B) + 4 * D3;
+    static constexpr int PER_ELEM_BYTES = TB * (SZ_A + SZ_B) + 4 * D3;
     // elements per workgroup from the LDS budget (48 KB -> 3 workgroups per 160 KB CU)
     static constexpr int E = cclamp(kLdsBudget / PER_ELEM_BYTES, 1, 32);
     static constexpr int NS = (E * Q3 + kThreads - 1) / kThreads;  // qp slots per thread
@@ -116,17 +117,18 @@ __device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassReg
 
 // Store policy of a pass output: into LDS, or atomically / plainly into the global y.
 // `addr` is element-local (OUT + n + NCOL o).
+template <class T>
 struct LdsOut {
-    double *out;
+    T *out;
     int sz;
-    __device__ __forceinline__ void put(int e, int addr, double v) const { out[e * sz + addr] = v; }
+    __device__ __forceinline__ void put(int e, int addr, T v) const { out[e * sz + addr] = v; }
 };
-template <bool ATOMIC>
+template <bool ATOMIC, class T>
 struct GlobalOut {
-    double *y;
+    T *y;
     const int32_t *lmap;  // [E][D^3] global index per local node, -1 for absent elements
     int d3;
-    __device__ __forceinline__ void put(int e, int addr, double v) const
+    __device__ __forceinline__ void put(int e, int addr, T v) const
     {
         const int g = lmap[e * d3 + addr];
         if (g >= 0) {
@@ -255,6 +257,147 @@ __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevT
 #pragma unroll
                 for (int o = 0; o < O; ++o) out.put(eI[bi], P::OUT + nI[bi] + P::NCOL * o, acc[o]);
             }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ 16-bit MFMA executor
+// v_mfma_f32_16x16x16{f16,bf16}: lane l supplies A[l%16][4(l/16)+t] and B[4(l/16)+t][l%16]
+// (t = 0..3, four 16-bit values) and returns D[4(l/16)+v][l%16] (v = 0..3, FP32),
+// pinned by test_mfma_16bit_lane_layouts.  Used by the mixed-precision inner apply: the
+// LDS tensors hold FP32 values that are rounded to FP16/BF16 as they enter the MFMA,
+// and the products accumulate in FP32.
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short f32_to_bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (short)(u >> 16);
+}
+
+template <bool BF>
+struct Mfma16 {
+    using V = typename std::conditional<BF, bf16x4_t, half4_t>::type;
+    __device__ static __forceinline__ V pack(const float (&f)[4])
+    {
+        V v;
+        if constexpr (BF) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[t] = f32_to_bf16_rne(f[t]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) v[t] = (_Float16)f[t];
+        }
+        return v;
+    }
+    __device__ static __forceinline__ flt4_t mma(V a, V b, flt4_t c)
+    {
+        if constexpr (BF)
+            return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+        else
+            return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <class P>
+struct PassRegs16 {
+    static constexpr int K = P::NT * P::C;
+    static constexpr int KC = (K + 15) / 16;   // k chunks of 16
+    static constexpr int RB = (P::O + 15) / 16;  // 16-row blocks
+};
+
+template <class P, bool BF>
+__device__ __forceinline__ void load_a16(const DevTables *tab,
+                                         typename Mfma16<BF>::V (&a)[PassRegs16<P>::RB][PassRegs16<P>::KC], int lane)
+{
+    constexpr int K = PassRegs16<P>::K;
+#pragma unroll
+    for (int rb = 0; rb < PassRegs16<P>::RB; ++rb)
+#pragma unroll
+        for (int kc = 0; kc < PassRegs16<P>::KC; ++kc) {
+            float f[4];
+            const int o = 16 * rb + (lane & 15);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 16 * kc + 4 * (lane >> 4) + t;
+                f[t] = (o < P::O && k < K) ? (float)P::A(tab, o, k) : 0.0f;
+            }
+            a[rb][kc] = Mfma16<BF>::pack(f);
+        }
+}
+
+template <class P, int E, bool BF, class Out>
+__device__ __forceinline__ void mfma16_pass(const float *in, int szin,
+                                            const typename Mfma16<BF>::V (&a)[PassRegs16<P>::RB][PassRegs16<P>::KC],
+                                            const Out &out, int wave, int lane)
+{
+    using V = typename Mfma16<BF>::V;
+    constexpr int C = P::C, K = PassRegs16<P>::K, KC = PassRegs16<P>::KC, RB = PassRegs16<P>::RB;
+    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE;
+    constexpr int NR = (NTILE + kWaves - 1) / kWaves;
+    constexpr int BATCH = NR < kMfmaBatch ? NR : kMfmaBatch;
+    const int kl = lane >> 4, nl = lane & 15;
+    int lin[KC][4];
+    bool kval[KC][4];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 16 * kc + 4 * kl + t;
+            kval[kc][t] = k < K;
+            const int tt = k / C, c = k - tt * C;
+            lin[kc][t] = nl * C + (kval[kc][t] ? P::in_off(tt) + c : 0);
+        }
+    const int lout = P::OUT + nl + P::NCOL * 4 * kl;
+#pragma unroll 1
+    for (int r0 = 0; r0 < NR; r0 += BATCH) {
+        V bv[BATCH][KC];
+        int eS[BATCH], n0S[BATCH];
+        bool cv[BATCH];
+#pragma unroll
+        for (int bi = 0; bi < BATCH; ++bi) {
+            const int t = wave + kWaves * (r0 + bi);
+            const bool tv = (r0 + bi < NR) && t < NTILE;
+            const int e = tv ? t / TPE : 0;
+            const int n0 = tv ? (t - e * TPE) * 16 : 0;
+            eS[bi] = e;
+            n0S[bi] = n0;
+            cv[bi] = tv && (n0 + nl < P::NCOL);
+            const float *base = in + e * szin + n0 * C;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                float f[4];
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const float v = base[lin[kc][t4]];
+                    f[t4] = (cv[bi] && kval[kc][t4]) ? v : 0.0f;
+                }
+                bv[bi][kc] = Mfma16<BF>::pack(f);
+            }
+        }
+        flt4_t acc[BATCH][RB];
+#pragma unroll
+        for (int bi = 0; bi < BATCH; ++bi)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[bi][rb] = flt4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int bi = 0; bi < BATCH; ++bi)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) acc[bi][rb] = Mfma16<BF>::mma(a[rb][kc], bv[bi][kc], acc[bi][rb]);
+#pragma unroll
+        for (int bi = 0; bi < BATCH; ++bi) {
+            if (!cv[bi]) continue;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (16 * rb + 4 * kl + v < P::O)
+                        out.put(eS[bi], n0S[bi] + lout + P::NCOL * (16 * rb + v), acc[bi][rb][v]);
         }
     }
 }

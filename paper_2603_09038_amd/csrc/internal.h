@@ -51,6 +51,7 @@ struct pa_op {
     int device = 0;
     int32_t *d_elem_dofs = nullptr;  // [nelem][d^3]
     double *d_qdata = nullptr;       // [nelem][ncomp][q^3]
+    float *d_qdata32 = nullptr;      // FP32 copy of D for the mixed-precision apply (lazy)
     double *d_vert = nullptr;        // [nvert][3]
     int32_t *d_hex = nullptr;        // [nelem][8]
     int nvert = 0;
@@ -75,7 +76,9 @@ hipError_t launch_load(const pa_op *op, const double *fq, double *b, hipStream_t
 // apply: y += A x over the listed elements (elem_list == nullptr: all)
 hipError_t launch_apply(const pa_op *op, int variant, const double *x, double *y,
                         const int32_t *elem_list, int nlist, hipStream_t s, bool *supported);
+hipError_t launch_apply_lp(const pa_op *op, int fmt, const float *x, float *y, hipStream_t s, bool *supported);
 hipError_t launch_diag(const pa_op *op, double *diag, hipStream_t s);
+hipError_t launch_debug_mfma16(int bf, const float *A, const float *B, float *D, hipStream_t s);
 hipError_t launch_debug_mfma(int shape, const double *A, const double *B, double *D, hipStream_t s);
 // vector kernels (k_vec.hip)
 hipError_t vec_fill(double *y, double v, int64_t n, hipStream_t s);

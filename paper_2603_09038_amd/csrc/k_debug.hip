@@ -33,7 +33,51 @@ __global__ __launch_bounds__(64) void k_debug_mfma4(const double *__restrict__ A
     const double b = B[beta * 16 + (l >> 4) * 4 + (l & 3)];
     Draw[l] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, 0.0, 0, 0, 0);
 }
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+
+__device__ short to_bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+// v_mfma_f32_16x16x16{f16,bf16}: lane l supplies A[l%16][4(l/16)+t], B[4(l/16)+t][l%16].
+template <bool BF>
+__global__ __launch_bounds__(64) void k_debug_mfma16(const float *__restrict__ A, const float *__restrict__ B,
+                                                     float *__restrict__ Draw)
+{
+    const int l = threadIdx.x;
+    flt4_t acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (BF) {
+        bf16x4_t a, b;
+        for (int t = 0; t < 4; ++t) {
+            a[t] = to_bf16_rne(A[(l % 16) * 16 + 4 * (l / 16) + t]);
+            b[t] = to_bf16_rne(B[(4 * (l / 16) + t) * 16 + l % 16]);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    } else {
+        half4_t a, b;
+        for (int t = 0; t < 4; ++t) {
+            a[t] = (_Float16)A[(l % 16) * 16 + 4 * (l / 16) + t];
+            b[t] = (_Float16)B[(4 * (l / 16) + t) * 16 + l % 16];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+    }
+    for (int v = 0; v < 4; ++v) Draw[4 * l + v] = acc[v];
+}
 }  // namespace
+
+hipError_t launch_debug_mfma16(int bf, const float *A, const float *B, float *D, hipStream_t s)
+{
+    if (bf)
+        hipLaunchKernelGGL(k_debug_mfma16<true>, dim3(1), dim3(64), 0, s, A, B, D);
+    else
+        hipLaunchKernelGGL(k_debug_mfma16<false>, dim3(1), dim3(64), 0, s, A, B, D);
+    return hipGetLastError();
+}
 
 hipError_t launch_debug_mfma(int shape, const double *A, const double *B, double *D, hipStream_t s)
 {

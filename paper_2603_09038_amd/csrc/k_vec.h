@@ -12,16 +12,26 @@ struct CgScalars {
     int pad;
 };
 
+hipError_t vec_fill(float *y, float v, int64_t n, hipStream_t s);
+hipError_t vec_set_list(float *y, float v, const int32_t *list, int n, hipStream_t s);
 hipError_t vec_recip(double *y, const double *x, int64_t n, hipStream_t s);
-hipError_t vec_dot(const double *x, const double *y, int64_t n, double *partial, double *out, hipStream_t s);
+hipError_t vec_to_f32(float *y, const double *x, double scale, int64_t n, hipStream_t s);  // y = (float)(x*scale)
+hipError_t vec_axpy_f32(double *x, double a, const float *d, int64_t n, hipStream_t s);    // x += a*d
+hipError_t vec_maxabs(const double *x, int64_t n, double *partial, double *out, hipStream_t s);
+template <class T>
+hipError_t vec_dot(const T *x, const T *y, int64_t n, double *partial, double *out, hipStream_t s);
 
-// r = b - r_in (r holds A x on entry), p = dinv r, scalars rz = r.dinv r, hist[0] = r.r
-hipError_t cg_init(const double *b, double *r, double *p, const double *dinv, int64_t n, double *partial,
-                   CgScalars *sc, double *hist, hipStream_t s);
+// r = b - r_in (r holds A x on entry; b == nullptr: r kept), p = dinv r,
+// scalars rz = r.dinv r, hist[0] = r.r  (all sums in FP64)
+template <class T>
+hipError_t cg_init(const T *b, T *r, T *p, const T *dinv, int64_t n, double *partial, CgScalars *sc, double *hist,
+                   hipStream_t s);
 // alpha = rz / (p . Ap)
-hipError_t cg_alpha(const double *p, const double *Ap, int64_t n, double *partial, CgScalars *sc, hipStream_t s);
+template <class T>
+hipError_t cg_alpha(const T *p, const T *Ap, int64_t n, double *partial, CgScalars *sc, hipStream_t s);
 // x += alpha p, r -= alpha Ap, beta, p = dinv r + beta p; hist[2 it] = r.r, hist[2 it + 1] = breakdown flag
-hipError_t cg_update(double *x, double *r, double *p, const double *Ap, const double *dinv, int64_t n,
-                     double *partial, CgScalars *sc, double *hist, int it, hipStream_t s);
+template <class T>
+hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
+                     double *hist, int it, hipStream_t s);
 
 }  // namespace hexpa

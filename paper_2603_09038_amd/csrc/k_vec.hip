@@ -1,4 +1,6 @@
-// Vector kernels and the fused FP64 CG update kernels (deterministic two-stage reductions).
+// Vector kernels and the fused CG update kernels.  Vectors are FP64 or FP32 (the
+// mixed-precision inner solve); every reduction accumulates in FP64 with a fixed block
+// count and a fixed tree order, so sums are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include "k_vec.h"
@@ -9,7 +11,8 @@ namespace {
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-__global__ void k_fill(double *y, double v, int64_t n)
+template <class T>
+__global__ void k_fill(T *y, T v, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = v;
 }
@@ -17,7 +20,8 @@ __global__ void k_copy(double *y, const double *x, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = x[i];
 }
-__global__ void k_set_list(double *y, double v, const int32_t *list, int n)
+template <class T>
+__global__ void k_set_list(T *y, T v, const int32_t *list, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[list[i]] = v;
@@ -28,7 +32,7 @@ __global__ void k_copy_list(double *y, const double *x, const int32_t *list, int
     if (i < n) y[list[i]] = x[list[i]];
 }
 
-// Block-wide sum of NV values per thread in a fixed tree order (bitwise reproducible).
+// Block-wide sum of NV values per thread in a fixed tree order.
 template <int NV>
 __device__ inline void block_sum(double (&v)[NV], double *sh /*[NV][256]*/)
 {
@@ -46,15 +50,44 @@ __device__ inline void block_sum(double (&v)[NV], double *sh /*[NV][256]*/)
     for (int k = 0; k < NV; ++k) v[k] = sh[k * 256];
 }
 
-// partial[b] = sum over this block's strided range of x.y
-__global__ void k_dot_partial(const double *__restrict__ x, const double *__restrict__ y, int64_t n, double *partial)
+template <class T>
+__global__ void k_dot_partial(const T *__restrict__ x, const T *__restrict__ y, int64_t n, double *partial)
 {
     __shared__ double sh[256];
     double v[1] = {0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        v[0] = fma(x[i], y[i], v[0]);
+        v[0] = fma((double)x[i], (double)y[i], v[0]);
     block_sum<1>(v, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+__global__ void k_maxabs_partial(const double *__restrict__ x, int64_t n, double *partial)
+{
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, fabs(x[i]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_max_to(const double *partial, int nb, double *out)
+{
+    __shared__ double sh[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) m = fmax(m, partial[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
 }
 
 __global__ void k_reduce_to(const double *partial, int nb, int stride, double *out)
@@ -86,20 +119,20 @@ __global__ void k_cg_alpha(const double *partial, int nb, CgScalars *s)
 }
 
 // x += alpha p; r -= alpha Ap; partial sums of (r . dinv r) and (r . r).
-__global__ void k_cg_update1(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
-                             const double *__restrict__ Ap, const double *__restrict__ dinv, int64_t n,
-                             const CgScalars *__restrict__ s, double *partial)
+template <class T>
+__global__ void k_cg_update1(T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ Ap,
+                             const T *__restrict__ dinv, int64_t n, const CgScalars *__restrict__ s, double *partial)
 {
     __shared__ double sh[2 * 256];
     const double alpha = s->alpha;
     double v[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        x[i] = fma(alpha, p[i], x[i]);
-        const double ri = fma(-alpha, Ap[i], r[i]);
+        x[i] = (T)fma(alpha, (double)p[i], (double)x[i]);
+        const T ri = (T)fma(-alpha, (double)Ap[i], (double)r[i]);
         r[i] = ri;
-        const double zi = dinv ? dinv[i] * ri : ri;
-        v[0] = fma(ri, zi, v[0]);
-        v[1] = fma(ri, ri, v[1]);
+        const double zi = dinv ? (double)(dinv[i] * ri) : (double)ri;
+        v[0] = fma((double)ri, zi, v[0]);
+        v[1] = fma((double)ri, (double)ri, v[1]);
     }
     block_sum<2>(v, sh);
     if (threadIdx.x == 0) {
@@ -130,29 +163,32 @@ __global__ void k_cg_beta(const double *partial, int nb, CgScalars *s, double *r
 }
 
 // p = dinv r + beta p
-__global__ void k_cg_update2(double *__restrict__ p, const double *__restrict__ r, const double *__restrict__ dinv,
-                             int64_t n, const CgScalars *__restrict__ s)
+template <class T>
+__global__ void k_cg_update2(T *__restrict__ p, const T *__restrict__ r, const T *__restrict__ dinv, int64_t n,
+                             const CgScalars *__restrict__ s)
 {
     const double beta = s->beta;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double zi = dinv ? dinv[i] * r[i] : r[i];
-        p[i] = fma(beta, p[i], zi);
+        const double zi = dinv ? (double)(dinv[i] * r[i]) : (double)r[i];
+        p[i] = (T)fma(beta, (double)p[i], zi);
     }
 }
 
-// r = b - Ax (in place into Ax), and partial sums of r . dinv r and r . r; p = dinv r.
-__global__ void k_cg_init(const double *__restrict__ b, double *__restrict__ r, double *__restrict__ p,
-                          const double *__restrict__ dinv, int64_t n, double *partial)
+// r = b - r_in (r holds A x on entry; b == nullptr means x = 0, r = r_in unchanged ... ) and
+// partial sums of r . dinv r and r . r; p = dinv r.
+template <class T>
+__global__ void k_cg_init(const T *__restrict__ b, T *__restrict__ r, T *__restrict__ p, const T *__restrict__ dinv,
+                          int64_t n, double *partial)
 {
     __shared__ double sh[2 * 256];
     double v[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double ri = b[i] - r[i];
+        const T ri = b ? (T)(b[i] - r[i]) : r[i];
         r[i] = ri;
-        const double zi = dinv ? dinv[i] * ri : ri;
+        const T zi = dinv ? dinv[i] * ri : ri;
         p[i] = zi;
-        v[0] = fma(ri, zi, v[0]);
-        v[1] = fma(ri, ri, v[1]);
+        v[0] = fma((double)ri, (double)zi, v[0]);
+        v[1] = fma((double)ri, (double)ri, v[1]);
     }
     block_sum<2>(v, sh);
     if (threadIdx.x == 0) {
@@ -185,15 +221,28 @@ __global__ void k_recip(double *y, const double *x, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = 1.0 / x[i];
 }
+__global__ void k_to_f32(float *y, const double *x, double scale, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)(x[i] * scale);
+}
+__global__ void k_axpy_f32(double *x, double a, const float *d, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = fma(a, (double)d[i], x[i]);
+}
 
 }  // namespace
 
-hipError_t vec_fill(double *y, double v, int64_t n, hipStream_t s)
+template <class T>
+hipError_t vec_fill_t(T *y, T v, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(min(nblk(n), 8192u)), dim3(256), 0, s, y, v, n);
+    hipLaunchKernelGGL(k_fill<T>, dim3(min(nblk(n), 8192u)), dim3(256), 0, s, y, v, n);
     return hipGetLastError();
 }
+hipError_t vec_fill(double *y, double v, int64_t n, hipStream_t s) { return vec_fill_t<double>(y, v, n, s); }
+hipError_t vec_fill(float *y, float v, int64_t n, hipStream_t s) { return vec_fill_t<float>(y, v, n, s); }
 hipError_t vec_copy(double *y, const double *x, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -203,7 +252,13 @@ hipError_t vec_copy(double *y, const double *x, int64_t n, hipStream_t s)
 hipError_t vec_set_list(double *y, double v, const int32_t *list, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_set_list, dim3(nblk(n)), dim3(256), 0, s, y, v, list, n);
+    hipLaunchKernelGGL(k_set_list<double>, dim3(nblk(n)), dim3(256), 0, s, y, v, list, n);
+    return hipGetLastError();
+}
+hipError_t vec_set_list(float *y, float v, const int32_t *list, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_list<float>, dim3(nblk(n)), dim3(256), 0, s, y, v, list, n);
     return hipGetLastError();
 }
 hipError_t vec_zero_list(double *y, const int32_t *list, int n, hipStream_t s) { return vec_set_list(y, 0.0, list, n, s); }
@@ -218,33 +273,64 @@ hipError_t vec_recip(double *y, const double *x, int64_t n, hipStream_t s)
     hipLaunchKernelGGL(k_recip, dim3(min(nblk(n), 8192u)), dim3(256), 0, s, y, x, n);
     return hipGetLastError();
 }
-hipError_t vec_dot(const double *x, const double *y, int64_t n, double *partial, double *out, hipStream_t s)
+hipError_t vec_to_f32(float *y, const double *x, double scale, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, x, y, n, partial);
+    hipLaunchKernelGGL(k_to_f32, dim3(min(nblk(n), 8192u)), dim3(256), 0, s, y, x, scale, n);
+    return hipGetLastError();
+}
+hipError_t vec_axpy_f32(double *x, double a, const float *d, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpy_f32, dim3(min(nblk(n), 8192u)), dim3(256), 0, s, x, a, d, n);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t vec_dot(const T *x, const T *y, int64_t n, double *partial, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(256), 0, s, x, y, n, partial);
     hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(256), 0, s, partial, kRedBlocks, 1, out);
     return hipGetLastError();
 }
+template hipError_t vec_dot<double>(const double *, const double *, int64_t, double *, double *, hipStream_t);
+template hipError_t vec_dot<float>(const float *, const float *, int64_t, double *, double *, hipStream_t);
 
-hipError_t cg_init(const double *b, double *r, double *p, const double *dinv, int64_t n, double *partial,
-                   CgScalars *sc, double *hist, hipStream_t s)
+hipError_t vec_maxabs(const double *x, int64_t n, double *partial, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_init, dim3(kRedBlocks), dim3(256), 0, s, b, r, p, dinv, n, partial);
+    hipLaunchKernelGGL(k_maxabs_partial, dim3(kRedBlocks), dim3(256), 0, s, x, n, partial);
+    hipLaunchKernelGGL(k_max_to, dim3(1), dim3(256), 0, s, partial, kRedBlocks, out);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t cg_init(const T *b, T *r, T *p, const T *dinv, int64_t n, double *partial, CgScalars *sc, double *hist,
+                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(kRedBlocks), dim3(256), 0, s, b, r, p, dinv, n, partial);
     hipLaunchKernelGGL(k_cg_init_scalars, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc, hist);
     return hipGetLastError();
 }
-hipError_t cg_alpha(const double *p, const double *Ap, int64_t n, double *partial, CgScalars *sc, hipStream_t s)
+template <class T>
+hipError_t cg_alpha(const T *p, const T *Ap, int64_t n, double *partial, CgScalars *sc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, p, Ap, n, partial);
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(256), 0, s, p, Ap, n, partial);
     hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc);
     return hipGetLastError();
 }
-hipError_t cg_update(double *x, double *r, double *p, const double *Ap, const double *dinv, int64_t n,
-                     double *partial, CgScalars *sc, double *hist, int it, hipStream_t s)
+template <class T>
+hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
+                     double *hist, int it, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_update1, dim3(kRedBlocks), dim3(256), 0, s, x, r, p, Ap, dinv, n, sc, partial);
+    hipLaunchKernelGGL(k_cg_update1<T>, dim3(kRedBlocks), dim3(256), 0, s, x, r, p, Ap, dinv, n, sc, partial);
     hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc, hist, it);
-    hipLaunchKernelGGL(k_cg_update2, dim3(kRedBlocks), dim3(256), 0, s, p, r, dinv, n, sc);
+    hipLaunchKernelGGL(k_cg_update2<T>, dim3(kRedBlocks), dim3(256), 0, s, p, r, dinv, n, sc);
     return hipGetLastError();
 }
+#define HEXPA_INST(T)                                                                                           \
+    template hipError_t cg_init<T>(const T *, T *, T *, const T *, int64_t, double *, CgScalars *, double *,   \
+                                   hipStream_t);                                                               \
+    template hipError_t cg_alpha<T>(const T *, const T *, int64_t, double *, CgScalars *, hipStream_t);         \
+    template hipError_t cg_update<T>(T *, T *, T *, const T *, const T *, int64_t, double *, CgScalars *,      \
+                                     double *, int, hipStream_t);
+HEXPA_INST(double)
+HEXPA_INST(float)
 
 }  // namespace hexpa

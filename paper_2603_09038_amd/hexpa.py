@@ -20,12 +20,13 @@ PA_ERR_NOT_CONVERGED, PA_ERR_BREAKDOWN, PA_ERR_IO = -5, -6, -7
 PA_MASS, PA_DIFFUSION = 1, 2
 PA_COEFF_CONST, PA_COEFF_SINE, PA_COEFF_GRID = 0, 1, 2
 PA_VARIANT_MFMA, PA_VARIANT_VALU, PA_VARIANT_MFMA_COLORED = 0, 1, 2
-PA_CG_PLAIN, PA_CG_JACOBI = 0, 1
+PA_CG_PLAIN, PA_CG_JACOBI, PA_CG_MIXED_IR = 0, 1, 2
+PA_LP_FP16, PA_LP_BF16 = 0, 1
 
 # every symbol include/hexpa.h declares
-EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_constrained", "pa_diag", "pa_load", "pa_qpoints", "pa_nodes",
+EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_lp", "pa_apply_constrained", "pa_diag", "pa_load", "pa_qpoints", "pa_nodes",
            "pa_get_elem_dofs", "pa_get_ess", "pa_set_variant", "pa_info", "pa_destroy", "pa_last_error",
-           "cg_solve", "pa_debug_mfma_f64")
+           "cg_solve", "pa_debug_mfma_f64", "pa_debug_mfma16")
 
 
 class HexpaError(RuntimeError):
@@ -55,12 +56,14 @@ class Info(ctypes.Structure):
 
 class CgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_it", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("constrained", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("constrained", ctypes.c_int32), ("lp_fmt", ctypes.c_int32),
+                ("inner_max", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
 
 
 class CgResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res_recursive", ctypes.c_double),
-                ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("inner_iters_total", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 def _load():
@@ -74,6 +77,7 @@ def _load():
                      ctypes.POINTER(vp)],
         "pa_apply": [vp, vp, vp, vp],
         "pa_apply_add": [vp, vp, vp, vp],
+        "pa_apply_lp": [vp, vp, vp, i32, vp],
         "pa_apply_constrained": [vp, vp, vp, vp],
         "pa_diag": [vp, vp, i32, vp],
         "pa_load": [vp, vp, vp, vp],
@@ -85,6 +89,7 @@ def _load():
         "pa_info": [vp, ctypes.POINTER(Info)],
         "cg_solve": [vp, vp, vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgResult), vp],
         "pa_debug_mfma_f64": [i32, vp, vp, vp, vp],
+        "pa_debug_mfma16": [i32, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -184,6 +189,11 @@ def pa_apply_add(h, x, y, stream=None):
     _check(_lib.pa_apply_add(h, _dptr(x), _dptr(y), _stream(stream)))
 
 
+def pa_apply_lp(h, x, y, fmt=PA_LP_FP16, stream=None):
+    import torch
+    _check(_lib.pa_apply_lp(h, _dptr(x, torch.float32), _dptr(y, torch.float32), int(fmt), _stream(stream)))
+
+
 def pa_apply_constrained(h, x, y, stream=None):
     _check(_lib.pa_apply_constrained(h, _dptr(x), _dptr(y), _stream(stream)))
 
@@ -228,18 +238,23 @@ def pa_destroy(h):
 
 
 def cg_solve(h, b, x, rtol=1e-8, max_it=10000, mode=PA_CG_JACOBI, check_every=1, constrained=True,
-             stream=None, raise_on_fail=True):
-    o = CgOpts(float(rtol), int(max_it), int(mode), int(check_every), int(bool(constrained)))
+             lp_fmt=PA_LP_FP16, inner_max=200, inner_rtol=1e-2, stream=None, raise_on_fail=True):
+    o = CgOpts(float(rtol), int(max_it), int(mode), int(check_every), int(bool(constrained)), int(lp_fmt),
+               int(inner_max), float(inner_rtol))
     r = CgResult()
     rc = _lib.cg_solve(h, _dptr(b), _dptr(x), ctypes.byref(o), ctypes.byref(r), _stream(stream))
     if raise_on_fail:
         _check(rc)
     return {"rc": rc, "iters": r.iters, "status": r.status, "rel_res_recursive": r.rel_res_recursive,
-            "rel_res_true": r.rel_res_true, "seconds": r.seconds}
+            "rel_res_true": r.rel_res_true, "seconds": r.seconds, "inner_iters_total": r.inner_iters_total}
 
 
 def pa_debug_mfma_f64(shape, A, B, D, stream=None):
     _check(_lib.pa_debug_mfma_f64(int(shape), _dptr(A), _dptr(B), _dptr(D), _stream(stream)))
+
+
+def pa_debug_mfma16(bf16, A, B, D, stream=None):
+    _check(_lib.pa_debug_mfma16(int(bool(bf16)), _dptr(A), _dptr(B), _dptr(D), _stream(stream)))
 
 
 # ------------------------------------------------------------------ convenience
@@ -260,6 +275,12 @@ class PAOperator:
     def apply(self, x, y=None):
         y = self._vec() if y is None else y
         pa_apply(self.h, x, y)
+        return y
+
+    def apply_lp(self, x32, fmt=PA_LP_FP16, y=None):
+        import torch
+        y = torch.empty(self.ndof, dtype=torch.float32, device="cuda") if y is None else y
+        pa_apply_lp(self.h, x32, y, fmt)
         return y
 
     def apply_constrained(self, x, y=None):
