@@ -23,6 +23,43 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+def kernel_source_hash():
+    """SHA-256 over the HIP sources of the library (traffic figures are tied to it)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2603_09038_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tag):
+    """HBM bytes per launch from a committed rocprofv3 counter summary (profiles/<tag>.md),
+    or None when the summary is absent or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", tag + ".md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def alg_bytes(ndof, nelem, p, q, ops):
     """Algorithmic HBM bytes of one apply: D (FP64), the int32 DOF map, read x, write y."""
     ncomp = (6 if ops & 2 else 0) + (1 if ops & 1 else 0)
@@ -64,7 +101,8 @@ def cpu_baseline(mesh, p, q, coeff_o, ops_o, ndof, nelem, budget_s):
     P = oracle.Problem(mesh, p, q, coeff=coeff_o, ops=ops_o)
     x = np.random.default_rng(7).uniform(-1, 1, ndof)
     rng = np.random.default_rng(11)
-    n_try = 16
+    n_try = 8 * max(1, oracle.num_threads())
+    P.apply(x, subset=np.sort(rng.choice(nelem, 8, replace=False)))  # warm the thread pool
     t0 = time.perf_counter()
     P.apply(x, subset=np.sort(rng.choice(nelem, n_try, replace=False)))
     t_try = time.perf_counter() - t0
@@ -98,6 +136,45 @@ def run_cg(hexpa, mesh, coeff, p, q):
             "rel_res_true": res["rel_res_true"], "status": res["rc"], "max_nodal_error_vs_exact_u": err}
 
 
+def run_mixed(hexpa, n=32, p=6, q=8):
+    """Log-normal coefficient (sigma = 1, correlation length 0.1, draw 0), Dirichlet,
+    b = A_c x* with x* the nodal interpolant of sin(pi x) sin(pi y) sin(pi z): FP64
+    Jacobi-PCG against FP64 iterative refinement with the FP16 / BF16 inner solver."""
+    import torch
+    import synth
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    grid, contrast = synth.lognormal_kappa_grid(0, sigma=1.0, ell=0.1)
+    op = hexpa.PAOperator(mesh, p, q, coeff={"kind": hexpa.PA_COEFF_GRID, "grid": grid}, ops=hexpa.PA_DIFFUSION,
+                          ess_mode=1)
+    xs = torch.tensor(synth.u_manufactured(op.nodes().cpu().numpy()), device="cuda")
+    b = op.apply_constrained(xs)
+    out = {"workload": f"{n}^3 perturbed hex mesh, p={p}, Q={q}, log-normal kappa (contrast {contrast:.0f}), "
+                       f"Dirichlet, b = A x*", "ndof": op.ndof}
+    # warm the kernels (and the lazily built FP32 D)
+    for fmt in (hexpa.PA_LP_FP16, hexpa.PA_LP_BF16):
+        x = torch.zeros_like(b)
+        hexpa.cg_solve(op.h, b, x, rtol=1e-2, max_it=1, mode=hexpa.PA_CG_MIXED_IR, lp_fmt=fmt, inner_max=5,
+                       raise_on_fail=False)
+    for tol in (1e-8, 1e-10):
+        x = torch.zeros_like(b)
+        r = hexpa.cg_solve(op.h, b, x, rtol=tol, max_it=50000, mode=hexpa.PA_CG_JACOBI, raise_on_fail=False)
+        err = float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs))
+        out[f"fp64_pcg_{tol:.0e}"] = {"seconds": r["seconds"], "iters": r["iters"], "rel_res_true": r["rel_res_true"],
+                                      "rel_err_vs_xstar": err, "status": r["rc"]}
+        for name, fmt in (("fp16", hexpa.PA_LP_FP16), ("bf16", hexpa.PA_LP_BF16)):
+            x = torch.zeros_like(b)
+            r = hexpa.cg_solve(op.h, b, x, rtol=tol, max_it=200, mode=hexpa.PA_CG_MIXED_IR, lp_fmt=fmt,
+                               inner_rtol=1e-2, inner_max=2000, raise_on_fail=False)
+            err = float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs))
+            out[f"mixed_{name}_{tol:.0e}"] = {"seconds": r["seconds"], "outer": r["iters"],
+                                             "inner_iters": r["inner_iters_total"], "rel_res_true": r["rel_res_true"],
+                                             "rel_err_vs_xstar": err, "status": r["rc"]}
+        out[f"speedup_fp16_{tol:.0e}"] = out[f"fp64_pcg_{tol:.0e}"]["seconds"] / out[f"mixed_fp16_{tol:.0e}"]["seconds"]
+        out[f"speedup_bf16_{tol:.0e}"] = out[f"fp64_pcg_{tol:.0e}"]["seconds"] / out[f"mixed_bf16_{tol:.0e}"]["seconds"]
+    op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +183,9 @@ def main():
     ap.add_argument("--variant", default="auto", choices=["auto", "mfma", "valu", "colored"])
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0 = skip)")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--sweep", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -117,6 +197,14 @@ def main():
     import synth
     from paper_2603_09038_amd import hexpa
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": a.numel() * 8}), flush=True)
+        return
 
     n, p, q = 48, 4, 6
     mesh = synth.box_mesh(n, perturb=0.1, seed=0)
@@ -144,6 +232,7 @@ def main():
     ms_step = 1e3 * wall / args.steps
     gdofs = ndof / (wall / args.steps) / 1e9
 
+    log(f"timed {args.steps} applies: {ms_step:.4f} ms/step")
     k_mean_ms, k_med_ms = time_kernel(op, hexpa, x, y, args.steps, 3)
     ab = alg_bytes(ndof, nelem, p, q, 2)
     achieved = ab / (k_mean_ms * 1e-3) / 1e9
@@ -156,7 +245,8 @@ def main():
                                "kappa=1+0.5sin(2pi x)sin(2pi y)sin(2pi z), x~U[-1,1]",
                    "ndof": ndof, "nelem": nelem, "p": p, "q1d": q, "variant": used},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"k_apply_c2_p4_diffusion_{used}_hbm_traffic"),
                      "kernel": f"k_apply<D=5,Q=6,diffusion,{used}>", "alg_bytes_per_launch": ab,
                      "alg_bytes_per_dof": ab / ndof, "kernel_ms_mean": k_mean_ms, "kernel_ms_median": k_med_ms,
                      "kernel_gdofs": ndof / (k_mean_ms * 1e-3) / 1e9,
@@ -164,7 +254,11 @@ def main():
     }
     if not args.no_cg:
         out["cg"] = run_cg(hexpa, mesh, coeff, p, q)
+        log(f"C2 Jacobi-PCG: {out['cg']['iters']} iterations, {out['cg']['seconds']:.3f} s")
     op.close()
+    if not args.no_mixed:
+        out["mixed"] = run_mixed(hexpa)
+        log("mixed-precision comparison done")
     if args.sweep:
         sweep = []
         for pp, nn in ((2, 155), (4, 78), (6, 52), (8, 40)):
@@ -181,12 +275,14 @@ def main():
                               "kernel_ms": km, "gdofs": o2.ndof / (km * 1e-3) / 1e9,
                               "hbm_frac": ab2 / (km * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               "variant": VNAME[o2.info["variant"]]})
+                log(f"sweep p={pp} ops={ops}: {sweep[-1]['gdofs']:.2f} GDOF/s")
                 o2.close()
                 del x2, y2
                 torch.cuda.empty_cache()
         out["sweep"] = sweep
     if args.cpu_budget > 0:
         import oracle
+        log("CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(mesh, p, q, oracle.Coeff.sine(), oracle.DIFFUSION, ndof, nelem,
                                            args.cpu_budget)
     print(json.dumps(out), flush=True)
