@@ -58,6 +58,13 @@ class Coeff:
         gz, gy, gx = (0, 0, 0) if grid is None else self.grid.shape
         self.c = _Coeff(kind, value, amp, freq, None if grid is None else self.grid.ctypes.data, gx, gy, gz)
 
+    def at(self, xyz):
+        """kappa at physical points xyz [n][3]."""
+        xyz = _f64(xyz).reshape(-1, 3)
+        out = np.zeros(xyz.shape[0])
+        lib().orc_coeff_points(ctypes.byref(self.c), ctypes.c_int64(xyz.shape[0]), _p(xyz), _p(out))
+        return out
+
     @staticmethod
     def const(v=1.0):
         return Coeff(COEFF_CONST, value=v)

@@ -105,29 +105,28 @@ def precond_nn(net, r, logk_tiles, elem_dofs, d, ndof, ess=None):
     return z, (x0, s)
 
 
-def loss_and_grads(net, r, t, logk_tiles, elem_dofs, d, ndof, ess):
-    """L = ||z - t||^2 / ||t||^2 over the free DOFs, z the network part of the preconditioner;
-    returns L and dL/d(parameters)."""
+def loss_and_grads(net, r, t, logk_tiles, elem_dofs, d, ndof, ess, Amul=None):
+    """Loss of the network part z of the preconditioner against the target t and its
+    gradient w.r.t. the parameters:
+        Amul None:  L = ||z - t||^2 / ||t||^2                 (free DOFs)
+        Amul given: L = (z - t)^T A (z - t) / t^T A t          (A = Amul, symmetric)
+    with dL/dz = 2 (z - t) / ||t||^2, resp. 2 A (z - t) / t^T A t, pulled back through the
+    averaging W, the scaling by s_e and the network."""
     z, (x0, s) = precond_nn(net, r, logk_tiles, elem_dofs, d, ndof, ess)
     free = ~ess
-    tt = float(t[free] @ t[free])
     diff = np.where(free, z - t, 0.0)
-    L = float(diff @ diff) / tt
-    gz = 2.0 * diff / tt                              # dL/dz
+    tf = np.where(free, t, 0.0)
+    if Amul is None:
+        Ad, At = diff, tf
+    else:
+        Ad, At = Amul(diff), Amul(tf)
+    den = float(tf @ At)
+    L = float(diff @ Ad) / den
+    gz = np.where(free, 2.0 * Ad / den, 0.0)          # dL/dz
     gz = gz / multiplicity(elem_dofs, ndof)           # through the averaging W
     gout = element_tiles(gz, elem_dofs, d) * s[:, None, None, None]  # through s_e * out
     grads, _ = net.backward(gout[:, None])
     return L, grads
-
-
-def init_params(cin, ch, seed=0):
-    """He-style initialisation (seeded), FP32-representable values."""
-    rng = np.random.default_rng([seed, 7])
-    W1 = rng.standard_normal((ch, cin, 3, 3, 3)) * np.sqrt(2.0 / (27 * cin))
-    W2 = rng.standard_normal((ch, ch, 3, 3, 3)) * np.sqrt(2.0 / (27 * ch))
-    W3 = rng.standard_normal((1, ch, 3, 3, 3)) * np.sqrt(1.0 / (27 * ch))
-    ps = [W1, np.zeros(ch), W2, np.zeros(ch), W3, np.zeros(1)]
-    return [p.astype(np.float32).astype(np.float64) for p in ps]
 
 
 def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

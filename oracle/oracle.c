@@ -562,6 +562,13 @@ int orc_load(int64_t nelem, const double *vert, const int32_t *hex, const int32_
     return 0;
 }
 
+/* Coefficient kappa at arbitrary physical points xyz [n][3] (the same evaluation the
+   element matrices use at the quadrature points). */
+void orc_coeff_points(const orc_coeff *cf, int64_t n, const double *xyz, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = coeff_at(cf, xyz + 3 * i);
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

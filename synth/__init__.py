@@ -8,7 +8,7 @@ parity comparison can borrow the other's method through it.
 
 Random streams use numpy's PCG64 seeded as ``default_rng([seed, stream])`` with
 stream 0 = mesh perturbation, 1 = input vector, 2 = coefficient field,
-3 = auxiliary field for training right-hand sides.
+3 = auxiliary field for training right-hand sides, 7 = network parameters.
 """
 from .fixtures import (  # noqa: F401
     box_mesh,
@@ -20,6 +20,9 @@ from .fixtures import (  # noqa: F401
     u_manufactured,
     f_manufactured,
     trilinear_sample,
+    net_params,
+    flat_params,
+    train_solution,
     STREAM_MESH,
     STREAM_X,
     STREAM_FIELD,

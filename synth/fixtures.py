@@ -133,3 +133,29 @@ def trilinear_sample(grid, xyz):
         wgt = (fx if a else 1 - fx) * (fy if b else 1 - fy) * (fz if cc else 1 - fz)
         out += wgt * grid[iz + cc, iy + b, ix + a]
     return out
+
+
+def net_params(cin=2, ch=16, seed=0):
+    """Random parameters of the 3-layer convolutional network (cin -> ch -> ch -> 1,
+    3x3x3 kernels): He-normal weights rounded to FP32, small random biases.  Layout
+    [W1 [ch][cin][3][3][3], b1 [ch], W2 [ch][ch][3][3][3], b2 [ch], W3 [1][ch][3][3][3], b3 [1]]."""
+    rng = _rng(seed, STREAM_AUX + 4)
+    W1 = rng.standard_normal((ch, cin, 3, 3, 3)) * np.sqrt(2.0 / (27 * cin))
+    W2 = rng.standard_normal((ch, ch, 3, 3, 3)) * np.sqrt(2.0 / (27 * ch))
+    W3 = rng.standard_normal((1, ch, 3, 3, 3)) * np.sqrt(1.0 / (27 * ch))
+    b1, b2, b3 = (0.1 * rng.standard_normal(k) for k in (ch, ch, 1))
+    ps = [W1, b1, W2, b2, W3, b3]
+    return [p.astype(np.float32).astype(np.float64) for p in ps]
+
+
+def flat_params(ps):
+    """The parameter list above as one flat FP32 vector (the library's layout)."""
+    return np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in ps])
+
+
+def train_solution(xyz, seed, ell=0.2, nfft=64):
+    """Known solution of a training system: sin(pi x) sin(pi y) sin(pi z) (1 + 0.5 g(x)),
+    g a unit-variance Gaussian random field (correlation length ell) drawn from
+    stream 3 with the given seed and sampled trilinearly at the points xyz [n][3]."""
+    g = grf_grid(seed, ell=ell, nfft=nfft, stream=STREAM_AUX)
+    return u_manufactured(xyz) * (1.0 + 0.5 * trilinear_sample(g, xyz))

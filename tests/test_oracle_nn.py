@@ -58,7 +58,7 @@ def _setup(p=2, n=2, seed=3):
 
 def test_network_gradients_against_central_differences():
     mesh, d, ed, ndof, ess, logk, r, t = _setup()
-    net = nn.Net(nn.init_params(2, 4, seed=1))
+    net = nn.Net(synth.net_params(2, 4, seed=1))
     L0, grads = nn.loss_and_grads(net, r, t, logk, ed, d, ndof, ess)
     rng = np.random.default_rng(5)
     h = 1e-6
@@ -78,7 +78,7 @@ def test_network_gradients_against_central_differences():
 
 def test_preconditioner_is_one_homogeneous_and_averages():
     mesh, d, ed, ndof, ess, logk, r, t = _setup()
-    net = nn.Net(nn.init_params(2, 4, seed=2))
+    net = nn.Net(synth.net_params(2, 4, seed=2))
     z1, _ = nn.precond_nn(net, r, logk, ed, d, ndof, ess)
     z2, _ = nn.precond_nn(net, 3.5 * r, logk, ed, d, ndof, ess)
     np.testing.assert_allclose(z2, 3.5 * z1, rtol=1e-12, atol=1e-14)
@@ -103,3 +103,31 @@ def test_adam_minimises_a_quadratic():
     m, v = [np.zeros(2)], [np.zeros(2)]
     q = nn.adam_step(p, [np.array([0.7, -1e-3])], m, v, 1, lr=0.1)
     np.testing.assert_allclose(q[0], [2.9, -1.9], rtol=0, atol=1e-6)
+
+
+def test_energy_loss_gradients_against_central_differences():
+    mesh, d, ed, ndof, ess, logk, r, t = _setup(p=2, n=2, seed=4)
+    P = oracle.Problem(mesh, 2, 4, coeff=oracle.Coeff.sine(), ops=oracle.DIFFUSION)
+    from oracle import solvers
+    Ac = solvers.constrained(P.apply, ess)
+    net = nn.Net(synth.net_params(2, 4, seed=3))
+    L0, grads = nn.loss_and_grads(net, r, t, logk, ed, d, ndof, ess, Amul=Ac)
+    assert 0.0 < L0
+    rng = np.random.default_rng(6)
+    h = 1e-6
+    for pi, Pm in enumerate(net.params()):
+        flat = Pm.reshape(-1)
+        for idx in rng.choice(flat.size, min(4, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            Lp, _ = nn.loss_and_grads(net, r, t, logk, ed, d, ndof, ess, Amul=Ac)
+            flat[idx] = old - h
+            Lm, _ = nn.loss_and_grads(net, r, t, logk, ed, d, ndof, ess, Amul=Ac)
+            flat[idx] = old
+            fd = (Lp - Lm) / (2 * h)
+            g = grads[pi].reshape(-1)[idx]
+            assert abs(fd - g) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (pi, idx, fd, g)
+    # the energy loss of t itself against 0 output is 1 (z = 0 network: all-zero parameters)
+    zero = nn.Net([np.zeros_like(q) for q in net.params()])
+    L1, _ = nn.loss_and_grads(zero, r, t, logk, ed, d, ndof, ess, Amul=Ac)
+    assert L1 == pytest.approx(1.0, rel=1e-14)
