@@ -160,6 +160,11 @@ const char *pa_last_error(void);
 #define PA_CG_JACOBI 1     /* Jacobi-preconditioned CG, M = diag(A_c) */
 #define PA_CG_MIXED_IR 2   /* FP64 iterative refinement around an inner Jacobi-PCG that runs
                               in FP32 vectors with the 16-bit-MFMA apply (pa_apply_lp) */
+#define PA_CG_FCG 3        /* flexible CG, FCG(1), preconditioned by a pa_lp handle (learned
+                              network and/or p = 1 coarse correction); on breakdown it falls
+                              back to Jacobi-PCG from the current iterate */
+
+typedef struct pa_lp pa_lp;
 
 typedef struct {
     double rtol;         /* stop when ||r_k||_2 <= rtol ||b||_2 (recursive residual; for
@@ -171,6 +176,13 @@ typedef struct {
     int32_t lp_fmt;      /* MIXED_IR: PA_LP_FP16 or PA_LP_BF16 */
     int32_t inner_max;   /* MIXED_IR: inner iterations per refinement step */
     double inner_rtol;   /* MIXED_IR: inner relative tolerance per refinement step */
+    pa_lp *lp;           /* FCG: the preconditioner, bound to this operator */
+    int32_t n_capture;   /* JACOBI: number of iterates to record (0: none) */
+    int32_t pad_;
+    const int32_t *capture_at; /* JACOBI: host [n_capture] ascending iteration numbers k >= 0 */
+    double *capture_x;         /* JACOBI: device [n_capture][ndof]; receives x_k when iteration k
+                                  ends (k = 0: the initial guess); rows of iterations not reached
+                                  are left untouched */
 } pa_cg_opts;
 
 typedef struct {
@@ -179,7 +191,7 @@ typedef struct {
     double rel_res_true;      /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
     double seconds;           /* wall time of the iteration (excludes diag and setup) */
     int32_t inner_iters_total; /* MIXED_IR: inner PCG iterations over all refinement steps */
-    int32_t pad;
+    int32_t fallback;          /* FCG: 1 if it broke down and finished as Jacobi-PCG */
 } pa_cg_result;
 
 /* Solve A x = b (or A_c x = b) by (preconditioned) CG (Saad, Alg. 9.1), all vector work
@@ -190,6 +202,73 @@ typedef struct {
    (x holds the last iterate) or PA_ERR_BREAKDOWN. */
 int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
              pa_cg_result *res, void *stream);
+
+/* ------------------------------------------------------------------ learned preconditioner
+   Two-level preconditioner for FCG on a structured box with diffusion (p + 1 in {3, 4, 5}):
+       z = W G^T NN(G r) + P1 A1^{-1} P1^T r,        then z = 0 on the essential DOFs.
+   NN: per element, a 3-layer convolutional network on the (p+1)^3 nodal tile
+   (3x3x3 cross-correlation, zero padding, bias; 2 -> 16 -> 16 -> 1 channels, ReLU between
+   layers) whose input channels are G_e r / s_e (s_e = RMS of G_e r over the tile) and
+   log kappa at the nodes, and whose output is multiplied by s_e, so the map is positively
+   1-homogeneous in r.  W = 1 / (number of elements sharing a DOF): element outputs are
+   averaged.  P1 = nodal interpolation from the p = 1 space on the same mesh, A1 = the p = 1
+   operator (same coefficient and operator bits, 3-point Gauss), constrained on the box
+   boundary; A1^{-1} is a fixed number of Jacobi-PCG iterations from 0 on A1's 27-point
+   stencil.  Network arithmetic is FP32 (parameters FP32); vectors FP64.
+   Parameters: flat FP32 array W1 [16][2][27], b1 [16], W2 [16][16][27], b2 [16],
+   W3 [1][16][27], b3 [1] with tap = tx + 3 ty + 9 tz for the neighbour
+   (i + tx - 1, j + ty - 1, k + tz - 1) of local node (i, j, k). */
+#define PA_LP_LOSS_ENERGY 0 /* L = (z - t)^T A_c (z - t) / t^T A_c t */
+#define PA_LP_LOSS_L2 1     /* L = ||z - t||^2 / ||t||^2 (free DOFs) */
+typedef struct {
+    int32_t use_net;      /* 1: network part; 0: Jacobi diag(A_c)^{-1} r in its place */
+    int32_t use_coarse;   /* 1: add the p = 1 coarse correction */
+    int32_t coarse_iters; /* Jacobi-PCG iterations of the coarse solve, >= 1 */
+    int32_t loss;         /* PA_LP_LOSS_* */
+    int32_t seed;         /* seed of the default (He-normal) parameter initialisation */
+    int32_t pad_;
+    double lr;            /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+} pa_lp_opts;
+
+/* Create a preconditioner bound to op (which must outlive the binding): builds the coarse
+   operator and its stencil, the log-kappa tiles and the DOF multiplicities.  Synchronous. */
+int pa_lp_create(pa_op *op, const pa_lp_opts *opts, pa_lp **out);
+/* Re-bind to another operator with the same box, order and essential DOFs (a new
+   coefficient draw): rebuilds every operator-dependent array, keeps the parameters and
+   the Adam state.  Synchronous. */
+int pa_lp_bind(pa_lp *lp, pa_op *op);
+/* Change use_net, use_coarse, coarse_iters, loss and lr (seed is ignored). */
+int pa_lp_configure(pa_lp *lp, const pa_lp_opts *opts);
+int pa_lp_num_params(void);
+/* Copy the n = pa_lp_num_params() parameters to/from host memory; set also resets the
+   Adam moments and step counter.  Synchronous. */
+int pa_lp_get_params(pa_lp *lp, float *host, int n);
+int pa_lp_set_params(pa_lp *lp, const float *host, int n);
+/* The network's log-kappa input, device [nelem][(p+1)^3] FP32.  Asynchronous. */
+int pa_lp_logk(pa_lp *lp, float *dev_out);
+/* z = M(r) (the full preconditioner above), device FP64 [ndof]; r must vanish on the
+   essential DOFs.  Uses handle-owned work arrays: calls on one handle must not overlap.
+   Asynchronous. */
+int pa_lp_apply(pa_lp *lp, const double *r, double *z, void *stream);
+/* z = P1 A1^{-1} P1^T r only (zero on the essential DOFs).  Asynchronous. */
+int pa_lp_coarse(pa_lp *lp, const double *r, double *z, void *stream);
+/* z = W G^T NN(G r) only (zero on the essential DOFs).  Asynchronous. */
+int pa_lp_net(pa_lp *lp, const double *r, double *z, void *stream);
+/* Loss of the network part z_NN(r) against target t (device, zero on essential DOFs)
+   and its gradient w.r.t. the parameters, written to grad_host [n] if not NULL (the
+   handle's gradient buffer is overwritten).  Synchronous; *loss receives L. */
+int pa_lp_loss_grad(pa_lp *lp, const double *r, const double *t, double *loss, float *grad_host, void *stream);
+/* One training step on the pair from iterate xk of A_c x = b with known solution xstar:
+   r = b - A_c xk, e = xstar - xk, target t = e - (coarse part of M)(r) when the coarse
+   correction is on (else e); then loss, gradient and one Adam update.  If loss is not
+   NULL the call synchronises and stores L.  Asynchronous otherwise. */
+int pa_lp_train_step(pa_lp *lp, const double *b, const double *xstar, const double *xk, double *loss,
+                     void *stream);
+/* Parameters to/from a file: magic "HEXPALP1", int32 version 1, int32 count, the FP32
+   values, and a 64-bit FNV-1a checksum of them.  PA_ERR_IO on any mismatch. */
+int pa_lp_save(pa_lp *lp, const char *path);
+int pa_lp_load(pa_lp *lp, const char *path);
+void pa_lp_destroy(pa_lp *lp);
 
 /* ------------------------------------------------------------------ diagnostics */
 

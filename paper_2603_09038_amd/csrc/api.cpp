@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "capi_util.h"
 #include "internal.h"
 #include "k_vec.h"
 
@@ -70,45 +71,6 @@ hipError_t launch_apply_lp(const pa_op *op, int fmt, const float *x, float *y, h
 
 using namespace hexpa;
 
-#define PA_TRY try {
-#define PA_CATCH                                                  \
-    }                                                             \
-    catch (const std::bad_alloc &) {                              \
-        set_error("host allocation failed");                      \
-        return PA_ERR_ARG;                                        \
-    }                                                             \
-    catch (...) {                                                 \
-        set_error("unexpected host exception");                   \
-        return PA_ERR_ARG;                                        \
-    }
-
-#define HIP_OK(expr)                                                                   \
-    do {                                                                               \
-        hipError_t _e = (expr);                                                        \
-        if (_e != hipSuccess) {                                                        \
-            set_error(std::string(#expr) + " failed: " + hipGetErrorString(_e));       \
-            return PA_ERR_HIP;                                                         \
-        }                                                                              \
-    } while (0)
-
-static int arg_error(const char *msg)
-{
-    set_error(msg);
-    return PA_ERR_ARG;
-}
-
-static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
-
-static void dfree(void *p)
-{
-    if (p) (void)hipFree(p);
-}
-
-template <class T>
-static hipError_t dalloc(T **p, size_t n)
-{
-    return hipMalloc((void **)p, n * sizeof(T) + 16);
-}
 
 extern "C" const char *pa_last_error(void) { return g_err.c_str(); }
 
@@ -266,6 +228,7 @@ extern "C" int pa_setup(const pa_mesh_desc *m, int order, int q1d, const pa_coef
             cf.grid = op->d_grid; cf.gx = c->gx; cf.gy = c->gy; cf.gz = c->gz;
         }
     }
+    op->coeff = cf;
     int *d_bad = nullptr;
     HIP_OK(hipMalloc((void **)&d_bad, sizeof(int)));
     HIP_OK(hipMemsetAsync(d_bad, 0, sizeof(int), s));
@@ -283,7 +246,7 @@ extern "C" int pa_setup(const pa_mesh_desc *m, int order, int q1d, const pa_coef
     PA_CATCH
 }
 
-static int do_apply(pa_op *op, int variant, const double *x, double *y, hipStream_t s, bool zero_first = true)
+int hexpa::do_apply(pa_op *op, int variant, const double *x, double *y, hipStream_t s, bool zero_first)
 {
     bool ok = true;
     if (zero_first) HIP_OK(vec_fill(y, 0.0, op->ndof, s));
@@ -325,7 +288,7 @@ extern "C" int pa_apply_add(pa_op *op, const double *x, double *y, void *stream)
 }
 
 // y = A_c x; uses op->d_scratch for the masked input.
-static int do_apply_constrained(pa_op *op, const double *x, double *y, hipStream_t s)
+int hexpa::do_apply_constrained(pa_op *op, const double *x, double *y, hipStream_t s)
 {
     if (op->ness == 0) return do_apply(op, op->variant, x, y, s);
     HIP_OK(vec_copy(op->d_scratch, x, op->ndof, s));
@@ -514,13 +477,14 @@ struct PcgWork {
     }
 };
 
-// (P)CG iterations from an initialised state (r, p, scalars, hist[0] = r0.r0 read back as
-// rr0).  Stops when r.r <= tol2, on breakdown, or after max_it.  The host inspects the
-// residual of the previous check while the next iteration is already queued, so the
-// device never idles waiting for the host.
-template <class T, class ApplyF>
-int pcg_iterate(ApplyF apply, T *x, const T *dinv, int64_t n, double tol2, int max_it, int check, PcgWork<T> &w,
-                hipStream_t s, double rr0, int *iters, double *rr_out)
+// Runs step(it) for it = 1, 2, ... from an initialised state (hist[0] = r0.r0 read back
+// as rr0); each step records hist[2 it] = r.r and hist[2 it + 1] = breakdown flag.  Stops
+// when r.r <= tol2, on breakdown, or after max_it.  The host inspects the residual of the
+// previous check while the next iteration is already queued, so the device never idles
+// waiting for the host.
+template <class T, class StepF>
+int lagged_iterate(StepF step, double tol2, int max_it, int check, PcgWork<T> &w, hipStream_t s, double rr0,
+                   int *iters, double *rr_out)
 {
     double rr = rr0;
     int it = 0, status = PA_ERR_NOT_CONVERGED;
@@ -528,10 +492,8 @@ int pcg_iterate(ApplyF apply, T *x, const T *dinv, int64_t n, double tol2, int m
     int pending = -1, nchecks = 0;
     while (status == PA_ERR_NOT_CONVERGED && it < max_it) {
         ++it;
-        int rc = apply(w.p, w.Ap);
+        int rc = step(it);
         if (rc) return rc;
-        HIP_OK(cg_alpha<T>(w.p, w.Ap, n, w.partial, w.sc, s));
-        HIP_OK(cg_update<T>(x, w.r, w.p, w.Ap, dinv, n, w.partial, w.sc, w.hist, it, s));
         if (it % check == 0 || it == max_it) {
             const int slot = (nchecks++) & 1;
             HIP_OK(hipMemcpyAsync(w.h_hist + 2 * slot, w.hist + 2 * (size_t)it, 2 * sizeof(double),
@@ -555,6 +517,26 @@ int pcg_iterate(ApplyF apply, T *x, const T *dinv, int64_t n, double tol2, int m
     *iters = it;
     *rr_out = rr;
     return status;
+}
+
+struct NoHook {
+    int operator()(int) const { return PA_OK; }
+};
+
+// (P)CG iterations (Saad, Alg. 9.1) with Jacobi dinv (nullptr: none); after(it) runs once
+// iteration it has been enqueued.
+template <class T, class ApplyF, class AfterF = NoHook>
+int pcg_iterate(ApplyF apply, T *x, const T *dinv, int64_t n, double tol2, int max_it, int check, PcgWork<T> &w,
+                hipStream_t s, double rr0, int *iters, double *rr_out, AfterF after = AfterF())
+{
+    auto step = [&](int it) -> int {
+        int rc = apply(w.p, w.Ap);
+        if (rc) return rc;
+        HIP_OK(cg_alpha<T>(w.p, w.Ap, n, w.partial, w.sc, s));
+        HIP_OK(cg_update<T>(x, w.r, w.p, w.Ap, dinv, n, w.partial, w.sc, w.hist, it, s));
+        return after(it);
+    };
+    return lagged_iterate<T>(step, tol2, max_it, check, w, s, rr0, iters, rr_out);
 }
 }  // namespace
 
@@ -660,13 +642,89 @@ static int solve_mixed_ir(pa_op *op, const double *b, double *x, const pa_cg_opt
     return status;
 }
 
+// Flexible CG, FCG(1) (Notay 2000): beta_k = (z_{k+1}, r_{k+1} - r_k) / (z_k, r_k) with a
+// variable (here nonlinear) preconditioner z = M(r).  On breakdown it restarts as
+// Jacobi-PCG from the current iterate for the remaining iterations.
+static int solve_fcg(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res, hipStream_t s,
+                     double bnorm, PcgWork<double> &w, const double *dinv)
+{
+    pa_lp *lp = o->lp;
+    if (!lp) return arg_error("cg_solve: PA_CG_FCG needs opts->lp");
+    if (lp_operator(lp) != op) return arg_error("cg_solve: the pa_lp handle is bound to another operator");
+    const int64_t n = op->ndof;
+    const bool con = o->constrained != 0;
+    const int check = o->check_every < 1 ? 1 : o->check_every;
+    double *z = nullptr, *rold = nullptr;
+    HIP_OK(dalloc(&z, n));
+    std::unique_ptr<void, void (*)(void *)> g1(z, dfree);
+    HIP_OK(dalloc(&rold, n));
+    std::unique_ptr<void, void (*)(void *)> g2(rold, dfree);
+    int rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);
+    if (rc) return rc;
+    HIP_OK(cg_init<double>(b, w.r, w.p, nullptr, n, w.partial, w.sc, w.hist, s));  // r = b - A x, hist[0] = r.r
+    HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double rr0 = w.h_hist[0];
+    const double tol2 = (o->rtol * bnorm) * (o->rtol * bnorm);
+    auto t0 = std::chrono::steady_clock::now();
+    rc = lp_precondition(lp, w.r, z, s);
+    if (rc) return rc;
+    HIP_OK(fcg_direction(z, w.r, nullptr, w.p, n, w.partial, w.sc, s));
+    auto step = [&](int it) -> int {
+        int r2 = cg_apply(op, con, w.p, w.Ap, s);
+        if (r2) return r2;
+        HIP_OK(cg_alpha<double>(w.p, w.Ap, n, w.partial, w.sc, s));
+        HIP_OK(fcg_update(x, w.r, rold, w.p, w.Ap, n, w.partial, w.sc, w.hist, it, s));
+        r2 = lp_precondition(lp, w.r, z, s);
+        if (r2) return r2;
+        HIP_OK(fcg_direction(z, w.r, rold, w.p, n, w.partial, w.sc, s));
+        return PA_OK;
+    };
+    int it = 0;
+    double rr = 0.0;
+    int status = lagged_iterate<double>(step, tol2, o->max_it, check, w, s, rr0, &it, &rr);
+    if (status != PA_OK && status != PA_ERR_NOT_CONVERGED && status != PA_ERR_BREAKDOWN) return status;
+    res->fallback = 0;
+    if (status == PA_ERR_BREAKDOWN && it < o->max_it) {
+        // Jacobi-PCG from the current iterate
+        res->fallback = 1;
+        rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);
+        if (rc) return rc;
+        HIP_OK(cg_init<double>(b, w.r, w.p, dinv, n, w.partial, w.sc, w.hist, s));
+        HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        int it2 = 0;
+        auto apply64 = [&](const double *p, double *y) { return cg_apply(op, con, p, y, s); };
+        status = pcg_iterate<double>(apply64, x, dinv, n, tol2, o->max_it - it, check, w, s, w.h_hist[0], &it2, &rr);
+        if (status != PA_OK && status != PA_ERR_NOT_CONVERGED && status != PA_ERR_BREAKDOWN) return status;
+        it += it2;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    res->seconds = std::chrono::duration<double>(t1 - t0).count();
+    res->iters = it;
+    res->rel_res_recursive = std::sqrt(rr) / bnorm;
+    double trel = 0.0;
+    rc = true_residual(op, con, b, x, w.Ap, w.r, w, bnorm, s, &trel);
+    if (rc) return rc;
+    res->rel_res_true = trel;
+    res->status = status;
+    if (status == PA_ERR_NOT_CONVERGED) set_error("cg_solve: max_it reached before rtol");
+    if (status == PA_ERR_BREAKDOWN) set_error("cg_solve: breakdown in FCG and in the Jacobi-PCG fallback");
+    return status;
+}
+
 extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res, void *stream)
 {
     PA_TRY
     if (!op || !b || !x || !o || !res) return arg_error("cg_solve: NULL argument");
     if (!(o->rtol > 0.0) || o->max_it < 1) return arg_error("cg_solve: need rtol > 0 and max_it >= 1");
-    if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI && o->mode != PA_CG_MIXED_IR)
+    if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI && o->mode != PA_CG_MIXED_IR && o->mode != PA_CG_FCG)
         return arg_error("cg_solve: unknown mode");
+    if (o->n_capture < 0 || (o->n_capture > 0 && (o->mode != PA_CG_JACOBI || !o->capture_at || !o->capture_x)))
+        return arg_error("cg_solve: capture needs PA_CG_JACOBI, capture_at and capture_x");
+    for (int j = 0; j < o->n_capture; ++j)
+        if (o->capture_at[j] < 0 || (j > 0 && o->capture_at[j] <= o->capture_at[j - 1]))
+            return arg_error("cg_solve: capture_at must be ascending and >= 0");
     std::memset(res, 0, sizeof(*res));
     hipStream_t s = as_stream(stream);
     const int64_t n = op->ndof;
@@ -696,6 +754,7 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
         return PA_OK;
     }
     if (o->mode == PA_CG_MIXED_IR) return solve_mixed_ir(op, b, x, o, res, s, bnorm, w, dinv);
+    if (o->mode == PA_CG_FCG) return solve_fcg(op, b, x, o, res, s, bnorm, w, dinv);
 
     // r = b - A x, p = M^{-1} r
     int rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);
@@ -708,7 +767,18 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     int it = 0;
     double rr = 0.0;
     auto apply64 = [&](const double *p, double *y) { return cg_apply(op, con, p, y, s); };
-    const int status = pcg_iterate<double>(apply64, x, dinv, n, tol2, o->max_it, check, w, s, w.h_hist[0], &it, &rr);
+    // iterates requested by the caller (training-data capture)
+    int cap = 0;
+    auto capture = [&](int k) -> int {
+        if (cap < o->n_capture && o->capture_at[cap] == k) {
+            HIP_OK(vec_copy(o->capture_x + (size_t)cap * n, x, n, s));
+            ++cap;
+        }
+        return PA_OK;
+    };
+    if ((rc = capture(0))) return rc;
+    const int status =
+        pcg_iterate<double>(apply64, x, dinv, n, tol2, o->max_it, check, w, s, w.h_hist[0], &it, &rr, capture);
     if (status != PA_OK && status != PA_ERR_NOT_CONVERGED && status != PA_ERR_BREAKDOWN) return status;
     auto t1 = std::chrono::steady_clock::now();
     res->seconds = std::chrono::duration<double>(t1 - t0).count();

@@ -56,7 +56,8 @@ struct pa_op {
     int32_t *d_hex = nullptr;        // [nelem][8]
     int nvert = 0;
     hexpa::DevTables *d_tab = nullptr;
-    double *d_grid = nullptr;        // coefficient grid (kept for pa_qpoints-free reuse)
+    double *d_grid = nullptr;        // coefficient grid (device copy)
+    hexpa::CoeffDev coeff{};         // coefficient as the kernels see it (grid -> d_grid)
     int32_t *d_ess = nullptr;        // [ness]
     // colour classes: elements of colour c are d_color_elems[color_off[c] .. color_off[c+1])
     int32_t *d_color_elems = nullptr;
@@ -72,6 +73,8 @@ namespace hexpa {
 hipError_t launch_setup_qdata(const pa_op *op, const CoeffDev &cf, int *d_bad, hipStream_t s);
 hipError_t launch_qpoints(const pa_op *op, double *xyz, hipStream_t s);
 hipError_t launch_nodes(const pa_op *op, double *xyz, hipStream_t s);
+// log kappa at every (element, local node) as FP32 [nelem][d^3]
+hipError_t logk_tiles(const pa_op *op, float *out, hipStream_t s);
 hipError_t launch_load(const pa_op *op, const double *fq, double *b, hipStream_t s);
 // apply: y += A x over the listed elements (elem_list == nullptr: all)
 hipError_t launch_apply(const pa_op *op, int variant, const double *x, double *y,
@@ -80,6 +83,13 @@ hipError_t launch_apply_lp(const pa_op *op, int fmt, const float *x, float *y, h
 hipError_t launch_diag(const pa_op *op, double *diag, hipStream_t s);
 hipError_t launch_debug_mfma16(int bf, const float *A, const float *B, float *D, hipStream_t s);
 hipError_t launch_debug_mfma(int shape, const double *A, const double *B, double *D, hipStream_t s);
+// host-side operator actions (api.cpp): y = A x over all elements (y zeroed first unless
+// zero_first is false), and y = A_c x with the essential rows/columns of the identity
+int do_apply(pa_op *op, int variant, const double *x, double *y, hipStream_t s, bool zero_first = true);
+int do_apply_constrained(pa_op *op, const double *x, double *y, hipStream_t s);
+// learned preconditioner (learned.cpp): z = M(r) and the operator the handle is bound to
+int lp_precondition(pa_lp *lp, const double *r, double *z, hipStream_t s);
+pa_op *lp_operator(const pa_lp *lp);
 // vector kernels (k_vec.hip)
 hipError_t vec_fill(double *y, double v, int64_t n, hipStream_t s);
 hipError_t vec_copy(double *y, const double *x, int64_t n, hipStream_t s);

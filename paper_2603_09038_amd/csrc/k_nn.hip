@@ -1,0 +1,702 @@
+// Kernels of the learned preconditioner: the per-element 3-layer convolutional network
+// on the (p+1)^3 nodal tile (3x3x3 cross-correlation, zero padding 1, bias, ReLU between
+// layers), its backward pass and Adam, the tile gather/normalisation and the averaged
+// scatter of the element outputs, and the p=1 coarse level of the two-level preconditioner.
+//
+// Activations are stored [element][channel][point], point = i + N j + N^2 k (the
+// operator's local node order); weights are [c_out][c_in][tap], tap = tx + 3 ty + 9 tz
+// reading the neighbour (i + tx - 1, j + ty - 1, k + tz - 1).  Work tiles sit in LDS with
+// a guard band on both sides so every shifted read is in bounds; reads that fall outside
+// the element are multiplied by 0 (zero padding).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "k_nn.h"
+
+namespace hexpa {
+
+namespace {
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <int N>
+struct Tile {
+    static constexpr int P = N * N * N;
+    static constexpr int GUARD = 1 + N + N * N;  // largest |offset| of a 3x3x3 neighbour
+    // elements per workgroup and workgroup size (a multiple of the wave size)
+    static constexpr int EPB = N == 3 ? 4 : (N == 4 ? 4 : 2);
+    static constexpr int THREADS = ((EPB * P + 63) / 64) * 64;
+    __host__ __device__ static constexpr int off(int tap)
+    {
+        return (tap % 3 - 1) + N * ((tap / 3) % 3 - 1) + N * N * (tap / 9 - 1);
+    }
+};
+
+// 0/1 factors of the 27 neighbours of point pt (1 inside the tile).
+template <int N>
+__device__ inline void tap_mask(int pt, float (&mk)[27])
+{
+    const int i = pt % N, j = (pt / N) % N, k = pt / (N * N);
+    const float mx[3] = {i > 0 ? 1.f : 0.f, 1.f, i < N - 1 ? 1.f : 0.f};
+    const float my[3] = {j > 0 ? 1.f : 0.f, 1.f, j < N - 1 ? 1.f : 0.f};
+    const float mz[3] = {k > 0 ? 1.f : 0.f, 1.f, k < N - 1 ? 1.f : 0.f};
+#pragma unroll
+    for (int t = 0; t < 27; ++t) mk[t] = mx[t % 3] * my[(t / 3) % 3] * mz[t / 9];
+}
+
+// out[e][o][pt] = bias[o] + sum_c sum_tap Wt[c][tap][o] in[e][c][pt + off(tap)]  (zero padded),
+// then ReLU (RELU) or a multiply by [a_mask > 0] (MASK, the backward of a ReLU).
+// Wt is the weight tensor already transposed to [c][tap][o]; bias may be null.
+template <int N, int CIN, int COUT, bool RELU, bool MASK>
+__global__ __launch_bounds__(Tile<N>::THREADS) void k_conv(int64_t nelem, const float *__restrict__ in,
+                                                           const float *__restrict__ Wt,
+                                                           const float *__restrict__ bias,
+                                                           const float *__restrict__ a_mask, float *__restrict__ out)
+{
+    using T = Tile<N>;
+    constexpr int NW = CIN * 27 * COUT, NX = T::EPB * CIN * T::P;
+    __shared__ float sw[NW];
+    __shared__ float sx[T::GUARD + NX + T::GUARD];
+    const int t = threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.x * T::EPB;
+    const int64_t nin = std::min((int64_t)T::EPB, nelem - e0) * CIN * T::P;
+    for (int i = t; i < NW; i += T::THREADS) sw[i] = Wt[i];
+    for (int i = t; i < T::GUARD; i += T::THREADS) sx[i] = sx[T::GUARD + NX + i] = 0.f;
+    for (int i = t; i < NX; i += T::THREADS) sx[T::GUARD + i] = i < nin ? in[e0 * CIN * T::P + i] : 0.f;
+    __syncthreads();
+    const int el = t / T::P, pt = t % T::P;
+    if (el >= T::EPB || e0 + el >= nelem) return;
+    float mk[27];
+    tap_mask<N>(pt, mk);
+    float acc[COUT];
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) acc[o] = bias ? bias[o] : 0.f;
+    const float *xs = sx + T::GUARD + el * CIN * T::P + pt;
+#pragma unroll 1
+    for (int c = 0; c < CIN; ++c) {
+        const float *xc = xs + c * T::P;
+        const float *wc = sw + c * 27 * COUT;
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) {
+            const float v = xc[T::off(tap)] * mk[tap];
+#pragma unroll
+            for (int o = 0; o < COUT; ++o) acc[o] = fmaf(wc[tap * COUT + o], v, acc[o]);
+        }
+    }
+    const int64_t ob = (e0 + el) * COUT * T::P + pt;
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) {
+        float v = acc[o];
+        if (RELU) v = fmaxf(v, 0.f);
+        if (MASK) v = a_mask[ob + o * T::P] > 0.f ? v : 0.f;
+        out[ob + o * T::P] = v;
+    }
+}
+
+// Wt[c][tap][o] = W[o][c][tap] (forward) or, for the input gradient, the flipped
+// adjoint Wt[o][tap][c] = W[o][c][26 - tap] read as a (COUT -> CIN) convolution.
+__global__ void k_transpose_w(const float *__restrict__ W, int cout, int cin, int adjoint, float *__restrict__ Wt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cout * cin * 27) return;
+    const int tap = i % 27, c = (i / 27) % cin, o = i / (27 * cin);
+    if (!adjoint) Wt[(c * 27 + tap) * cout + o] = W[i];
+    else Wt[(o * 27 + (26 - tap)) * cin + c] = W[i];
+}
+
+// Weight/bias gradient partial sums: dW[o][c][tap] = sum_e sum_pt dout[e][o][pt] in[e][c][pt + off(tap)],
+// db[o] = sum dout.  Thread = (c, group of OB outputs, slice of points); workgroup g
+// handles elements g, g + G, ...; row (g, slice) of `partial` receives the thread sums.
+template <int CIN, int COUT>
+struct WgradShape {
+    static constexpr int OB = COUT >= 4 ? 4 : 1;
+    static constexpr int NPAIR = CIN * (COUT / OB);
+    static constexpr int SL = 256 / NPAIR;
+    static constexpr int NT = COUT * CIN * 27 + COUT;
+    static_assert(COUT % OB == 0 && NPAIR <= 256 && 256 % NPAIR == 0, "thread layout");
+};
+constexpr int kWgradBlocks = 256;
+
+template <int N, int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_wgrad(int64_t nelem, const float *__restrict__ in,
+                                                    const float *__restrict__ dout, float *__restrict__ partial)
+{
+    using T = Tile<N>;
+    using S = WgradShape<CIN, COUT>;
+    constexpr int OB = S::OB, NX = CIN * T::P;
+    __shared__ float sx[T::GUARD + NX + T::GUARD];
+    __shared__ float sd[COUT * T::P];
+    const int t = threadIdx.x;
+    const int pair = t % S::NPAIR, sl = t / S::NPAIR;
+    const int c = pair % CIN, og = pair / CIN;
+    float acc[OB][27], bacc[OB];
+#pragma unroll
+    for (int u = 0; u < OB; ++u) {
+        bacc[u] = 0.f;
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) acc[u][tap] = 0.f;
+    }
+    for (int i = t; i < T::GUARD; i += 256) sx[i] = sx[T::GUARD + NX + i] = 0.f;
+    for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
+        __syncthreads();
+        for (int i = t; i < NX; i += 256) sx[T::GUARD + i] = in[e * NX + i];
+        for (int i = t; i < COUT * T::P; i += 256) sd[i] = dout[e * COUT * T::P + i];
+        __syncthreads();
+        for (int pt = sl; pt < T::P; pt += S::SL) {
+            float mk[27];
+            tap_mask<N>(pt, mk);
+            float g[OB];
+#pragma unroll
+            for (int u = 0; u < OB; ++u) {
+                g[u] = sd[(og * OB + u) * T::P + pt];
+                bacc[u] += g[u];
+            }
+            const float *xc = sx + T::GUARD + c * T::P + pt;
+#pragma unroll
+            for (int tap = 0; tap < 27; ++tap) {
+                const float v = xc[T::off(tap)] * mk[tap];
+#pragma unroll
+                for (int u = 0; u < OB; ++u) acc[u][tap] = fmaf(g[u], v, acc[u][tap]);
+            }
+        }
+    }
+    float *row = partial + ((int64_t)blockIdx.x * S::SL + sl) * S::NT;
+#pragma unroll
+    for (int u = 0; u < OB; ++u) {
+        const int o = og * OB + u;
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) row[(o * CIN + c) * 27 + tap] = acc[u][tap];
+        if (c == 0) row[COUT * CIN * 27 + o] = bacc[u];
+    }
+}
+
+// grad[w] += sum over rows of partial[row][w], rows in a fixed order (FP64 accumulation).
+__global__ void k_reduce_rows(const float *__restrict__ partial, int rows, int nt, float *__restrict__ grad)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nt) return;
+    double a = 0.0;
+    for (int g = 0; g < rows; ++g) a += partial[(int64_t)g * nt + w];
+    grad[w] += (float)a;
+}
+
+template <int N>
+__global__ __launch_bounds__(128) void k_nn_input(int64_t nelem, const double *__restrict__ r,
+                                                  const int32_t *__restrict__ emap, const float *__restrict__ logk,
+                                                  float *__restrict__ x0, float *__restrict__ s_out)
+{
+    constexpr int P = N * N * N;
+    static_assert(P <= 128, "one point per thread");
+    __shared__ double red[128];
+    const int64_t e = blockIdx.x;
+    const int t = threadIdx.x;
+    const double v = t < P ? r[emap[e * P + t]] : 0.0;
+    red[t] = v * v;
+    __syncthreads();
+    for (int h = 64; h > 0; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    const double rms = sqrt(red[0] / P);
+    const double s = rms > 0.0 ? rms : 1.0;
+    if (t < P) {
+        x0[(e * 2 + 0) * P + t] = (float)(v / s);
+        x0[(e * 2 + 1) * P + t] = logk[e * P + t];
+    }
+    if (t == 0) s_out[e] = (float)s;
+}
+
+__global__ void k_nn_output(int64_t total, int P, const float *__restrict__ out, const float *__restrict__ s,
+                            const int32_t *__restrict__ emap, const double *__restrict__ inv_mult,
+                            double *__restrict__ z)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int g = emap[idx];
+    unsafeAtomicAdd(z + g, (double)out[idx] * (double)s[idx / P] * inv_mult[g]);
+}
+
+__global__ void k_nn_output_grad(int64_t total, int P, const double *__restrict__ gz, const float *__restrict__ s,
+                                 const int32_t *__restrict__ emap, const double *__restrict__ inv_mult,
+                                 float *__restrict__ gout)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int g = emap[idx];
+    gout[idx] = (float)(gz[g] * inv_mult[g] * (double)s[idx / P]);
+}
+
+__global__ void k_count(int64_t total, const int32_t *__restrict__ emap, double *__restrict__ cnt)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < total) unsafeAtomicAdd(cnt + emap[idx], 1.0);
+}
+__global__ void k_recip_or_zero(int64_t n, double *__restrict__ v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = v[i] > 0.0 ? 1.0 / v[i] : 0.0;
+}
+__global__ void k_fill_f32(float *y, float v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = v;
+}
+
+__global__ void k_adam(float *__restrict__ p, float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int n, float lr, float bc1, float bc2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    g[i] = 0.0f;
+}
+
+__global__ void k_sub(double *y, const double *a, const double *b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a[i] - b[i];
+}
+__global__ void k_mul(double *y, const double *a, const double *b, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a[i] * b[i];
+}
+
+__global__ void k_loss_scale(double *g, int64_t n, double *sc)
+{
+    const double den = sc[1];
+    const double f = den > 0.0 ? 2.0 / den : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        g[i] *= f;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[2] = den > 0.0 ? sc[0] / den : 0.0;
+}
+
+// ---------------------------------------------------------------- coarse level
+// 1-D weight of coarse vertex a at fine lattice index I: the fine node lies in element
+// ex = min(I / p, n - 1) at GLL coordinate xi = gll[I - ex p]; the p=1 basis there is
+// (1 - xi) at vertex ex and xi at vertex ex + 1.
+__device__ inline double w1d(int64_t I, int64_t a, int n, int p, const double *gll)
+{
+    const int64_t ex = min(I / p, (int64_t)n - 1);
+    const double xi = gll[I - ex * p];
+    return a == ex ? 1.0 - xi : (a == ex + 1 ? xi : 0.0);
+}
+
+__global__ void k_prolong(BoxDims b, const double *__restrict__ gll, const double *__restrict__ u1,
+                          double *__restrict__ uf, int add)
+{
+    const int64_t Mx = (int64_t)b.nx * b.p + 1, My = (int64_t)b.ny * b.p + 1, Mz = (int64_t)b.nz * b.p + 1;
+    const int64_t Cx = b.nx + 1, Cy = b.ny + 1;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= Mx * My * Mz) return;
+    const int64_t I = g % Mx, J = (g / Mx) % My, K = g / (Mx * My);
+    const int64_t ex = min(I / b.p, (int64_t)b.nx - 1), ey = min(J / b.p, (int64_t)b.ny - 1),
+                  ez = min(K / b.p, (int64_t)b.nz - 1);
+    const double x = gll[I - ex * b.p], y = gll[J - ey * b.p], z = gll[K - ez * b.p];
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
+        const double w = (ca ? x : 1.0 - x) * (cb ? y : 1.0 - y) * (cc ? z : 1.0 - z);
+        v += w * u1[(ex + ca) + Cx * ((ey + cb) + Cy * (ez + cc))];
+    }
+    uf[g] = add ? uf[g] + v : v;
+}
+
+// r1[a,b,c] = sum over the fine nodes of the 2x2x2 coarse cells around the vertex of
+// w(I,a) w(J,b) w(K,c) rf[I,J,K]; fixed loop order, no atomics.
+__global__ void k_restrict(BoxDims b, const double *__restrict__ gll, const double *__restrict__ rf,
+                           double *__restrict__ r1)
+{
+    const int64_t Mx = (int64_t)b.nx * b.p + 1, My = (int64_t)b.ny * b.p + 1, Mz = (int64_t)b.nz * b.p + 1;
+    const int64_t Cx = b.nx + 1, Cy = b.ny + 1, Cz = b.nz + 1;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= Cx * Cy * Cz) return;
+    const int64_t a = v % Cx, bb = (v / Cx) % Cy, c = v / (Cx * Cy);
+    const int64_t I0 = max((int64_t)0, (a - 1) * b.p), I1 = min(Mx - 1, (a + 1) * b.p);
+    const int64_t J0 = max((int64_t)0, (bb - 1) * b.p), J1 = min(My - 1, (bb + 1) * b.p);
+    const int64_t K0 = max((int64_t)0, (c - 1) * b.p), K1 = min(Mz - 1, (c + 1) * b.p);
+    double acc = 0.0;
+    for (int64_t K = K0; K <= K1; ++K) {
+        const double wz = w1d(K, c, b.nz, b.p, gll);
+        if (wz == 0.0) continue;
+        for (int64_t J = J0; J <= J1; ++J) {
+            const double wyz = w1d(J, bb, b.ny, b.p, gll) * wz;
+            if (wyz == 0.0) continue;
+            const double *row = rf + Mx * (J + My * K);
+            for (int64_t I = I0; I <= I1; ++I) acc = fma(w1d(I, a, b.nx, b.p, gll) * wyz, row[I], acc);
+        }
+    }
+    r1[v] = acc;
+}
+
+__global__ void k_probe_vec(BoxDims b, int cls, double *__restrict__ v)
+{
+    const int64_t Cx = b.nx + 1, Cy = b.ny + 1, Cz = b.nz + 1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Cx * Cy * Cz) return;
+    const int64_t I = i % Cx, J = (i / Cx) % Cy, K = i / (Cx * Cy);
+    v[i] = (I % 3 == cls % 3 && J % 3 == (cls / 3) % 3 && K % 3 == cls / 9) ? 1.0 : 0.0;
+}
+
+// Within the 3x3x3 neighbourhood of vertex i exactly one vertex has class cls; the entry
+// of A v_cls at i is therefore A[i][j] for that neighbour j (0 if j is off the lattice).
+// S is stored [slot][i], slot = (dx+1) + 3 (dy+1) + 9 (dz+1).  Constrained rows and
+// columns (ess) become those of the identity.
+__global__ void k_probe_gather(BoxDims b, int cls, const double *__restrict__ y, const uint8_t *__restrict__ ess,
+                               double *__restrict__ S)
+{
+    const int64_t Cx = b.nx + 1, Cy = b.ny + 1, Cz = b.nz + 1, n1 = Cx * Cy * Cz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n1) return;
+    const int64_t I = i % Cx, J = (i / Cx) % Cy, K = i / (Cx * Cy);
+    auto delta = [](int64_t X, int want) {
+        const int d = (int)(((want - X) % 3 + 3) % 3);
+        return d == 2 ? -1 : d;
+    };
+    const int dx = delta(I, cls % 3), dy = delta(J, (cls / 3) % 3), dz = delta(K, cls / 9);
+    const int slot = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+    const int64_t In = I + dx, Jn = J + dy, Kn = K + dz;
+    double v = 0.0;
+    if (In >= 0 && In < Cx && Jn >= 0 && Jn < Cy && Kn >= 0 && Kn < Cz) {
+        const int64_t j = In + Cx * (Jn + Cy * Kn);
+        v = y[i];
+        if (ess && (ess[i] || ess[j])) v = (j == i && ess[i]) ? 1.0 : 0.0;
+    }
+    S[slot * n1 + i] = v;
+}
+
+__global__ void k_dinv_center(int64_t n1, const double *__restrict__ S, double *__restrict__ dinv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n1) dinv[i] = 1.0 / S[13 * n1 + i];
+}
+
+// Block sum in a fixed order; the last workgroup to finish adds the per-block partials in
+// block order and hands the total to fin (thread 0 only), then re-arms the counter.
+template <class F>
+__device__ inline void grid_sum_last(double v, double *partial, unsigned int *count, F fin)
+{
+    __shared__ double sh[256];
+    __shared__ int last;
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) sh[t] += sh[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        partial[blockIdx.x] = sh[0];
+        __threadfence();
+        const unsigned prev = atomicAdd(count, 1u);
+        last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double a = 0.0;
+    for (int i = t; i < (int)gridDim.x; i += 256)
+        a += __hip_atomic_load(partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sh[t] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) sh[t] += sh[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        fin(sh[0]);
+        __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// u = 0, z = dinv r, p0 = 0; rz = r.z, beta = 0
+__global__ __launch_bounds__(256) void k_cpcg_init(int64_t n1, const double *__restrict__ dinv,
+                                                   const double *__restrict__ r, double *__restrict__ u,
+                                                   double *__restrict__ z, double *__restrict__ p0, double *partial,
+                                                   CoarseScalars *sc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (i < n1) {
+        const double zi = dinv[i] * r[i];
+        z[i] = zi;
+        u[i] = 0.0;
+        p0[i] = 0.0;
+        v = r[i] * zi;
+    }
+    grid_sum_last(v, partial, &sc->count, [&](double tot) {
+        sc->rz = tot;
+        sc->beta = 0.0;
+    });
+}
+
+// p1 = z + beta p0; Ap = S (z + beta p0); alpha = rz / (p1 . Ap)
+__global__ __launch_bounds__(256) void k_cpcg_a(BoxDims b, const double *__restrict__ S,
+                                                const double *__restrict__ z, const double *__restrict__ p0,
+                                                double *__restrict__ p1, double *__restrict__ Ap, double *partial,
+                                                CoarseScalars *sc)
+{
+    const int64_t Cx = b.nx + 1, Cy = b.ny + 1, Cz = b.nz + 1, n1 = Cx * Cy * Cz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double beta = sc->beta;
+    double v = 0.0;
+    if (i < n1) {
+        const int64_t I = i % Cx, J = (i / Cx) % Cy, K = i / (Cx * Cy);
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < 27; ++s) {
+            const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = s / 9 - 1;
+            const int64_t In = I + dx, Jn = J + dy, Kn = K + dz;
+            if (In < 0 || In >= Cx || Jn < 0 || Jn >= Cy || Kn < 0 || Kn >= Cz) continue;
+            const int64_t j = i + dx + Cx * (dy + Cy * dz);
+            acc = fma(S[s * n1 + i], z[j] + beta * p0[j], acc);
+        }
+        const double pi = z[i] + beta * p0[i];
+        p1[i] = pi;
+        Ap[i] = acc;
+        v = pi * acc;
+    }
+    grid_sum_last(v, partial, &sc->count, [&](double tot) {
+        sc->pAp = tot;
+        sc->alpha = tot > 0.0 ? sc->rz / tot : 0.0;
+    });
+}
+
+// u += alpha p1; r -= alpha Ap; z = dinv r; beta = (r.z)_new / rz
+__global__ __launch_bounds__(256) void k_cpcg_b(int64_t n1, const double *__restrict__ dinv,
+                                                const double *__restrict__ p1, const double *__restrict__ Ap,
+                                                double *__restrict__ u, double *__restrict__ r,
+                                                double *__restrict__ z, double *partial, CoarseScalars *sc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double alpha = sc->alpha;
+    double v = 0.0;
+    if (i < n1) {
+        u[i] = fma(alpha, p1[i], u[i]);
+        const double ri = fma(-alpha, Ap[i], r[i]);
+        r[i] = ri;
+        const double zi = dinv[i] * ri;
+        z[i] = zi;
+        v = ri * zi;
+    }
+    grid_sum_last(v, partial, &sc->count, [&](double tot) {
+        sc->beta = sc->rz > 0.0 ? tot / sc->rz : 0.0;
+        sc->rz = tot;
+    });
+}
+
+template <int N>
+hipError_t forward_t(int64_t nelem, const float *params, float *wt, const float *x0, float *a1, float *a2,
+                     float *out, hipStream_t s)
+{
+    using T = Tile<N>;
+    const unsigned nb = (unsigned)((nelem + T::EPB - 1) / T::EPB);
+    float *w1 = wt, *w2 = wt + kNetW1, *w3 = w2 + kNetW2;
+    hipLaunchKernelGGL(k_transpose_w, dim3(nblk(kNetW1)), dim3(256), 0, s, params + kNetOffW1, kNetCh, kNetCin, 0, w1);
+    hipLaunchKernelGGL(k_transpose_w, dim3(nblk(kNetW2)), dim3(256), 0, s, params + kNetOffW2, kNetCh, kNetCh, 0, w2);
+    hipLaunchKernelGGL(k_transpose_w, dim3(nblk(kNetW3)), dim3(256), 0, s, params + kNetOffW3, 1, kNetCh, 0, w3);
+    hipLaunchKernelGGL((k_conv<N, kNetCin, kNetCh, true, false>), dim3(nb), dim3(T::THREADS), 0, s, nelem, x0, w1,
+                       params + kNetOffB1, nullptr, a1);
+    hipLaunchKernelGGL((k_conv<N, kNetCh, kNetCh, true, false>), dim3(nb), dim3(T::THREADS), 0, s, nelem, a1, w2,
+                       params + kNetOffB2, nullptr, a2);
+    hipLaunchKernelGGL((k_conv<N, kNetCh, 1, false, false>), dim3(nb), dim3(T::THREADS), 0, s, nelem, a2, w3,
+                       params + kNetOffB3, nullptr, out);
+    return hipGetLastError();
+}
+
+// grad_w holds the layer's weights followed by its biases: the order of a partial row.
+template <int N, int CIN, int COUT>
+void wgrad_layer(int64_t nelem, const float *in, const float *dout, float *partial, float *grad_w, hipStream_t s)
+{
+    using S = WgradShape<CIN, COUT>;
+    hipLaunchKernelGGL((k_conv_wgrad<N, CIN, COUT>), dim3(kWgradBlocks), dim3(256), 0, s, nelem, in, dout, partial);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(nblk(S::NT)), dim3(256), 0, s, partial, kWgradBlocks * S::SL, S::NT,
+                       grad_w);
+}
+
+template <int N>
+hipError_t backward_t(int64_t nelem, const float *params, const float *x0, const float *a1, const float *a2,
+                      const float *gout, float *ga2, float *ga1, float *grads, float *wt, float *partial,
+                      hipStream_t s)
+{
+    using T = Tile<N>;
+    const unsigned nb = (unsigned)((nelem + T::EPB - 1) / T::EPB);
+    // layer 3: weights, then the gradient w.r.t. a2 masked by the ReLU
+    wgrad_layer<N, kNetCh, 1>(nelem, a2, gout, partial, grads + kNetOffW3, s);
+    hipLaunchKernelGGL(k_transpose_w, dim3(nblk(kNetW3)), dim3(256), 0, s, params + kNetOffW3, 1, kNetCh, 1, wt);
+    hipLaunchKernelGGL((k_conv<N, 1, kNetCh, false, true>), dim3(nb), dim3(T::THREADS), 0, s, nelem, gout, wt,
+                       nullptr, a2, ga2);
+    // layer 2
+    wgrad_layer<N, kNetCh, kNetCh>(nelem, a1, ga2, partial, grads + kNetOffW2, s);
+    hipLaunchKernelGGL(k_transpose_w, dim3(nblk(kNetW2)), dim3(256), 0, s, params + kNetOffW2, kNetCh, kNetCh, 1, wt);
+    hipLaunchKernelGGL((k_conv<N, kNetCh, kNetCh, false, true>), dim3(nb), dim3(T::THREADS), 0, s, nelem, ga2, wt,
+                       nullptr, a1, ga1);
+    // layer 1 (the input needs no gradient)
+    wgrad_layer<N, kNetCin, kNetCh>(nelem, x0, ga1, partial, grads + kNetOffW1, s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t nn_partial_floats()
+{
+    using L1 = WgradShape<kNetCin, kNetCh>;
+    using L2 = WgradShape<kNetCh, kNetCh>;
+    using L3 = WgradShape<kNetCh, 1>;
+    return (int64_t)kWgradBlocks * std::max({L1::SL * L1::NT, L2::SL * L2::NT, L3::SL * L3::NT});
+}
+
+hipError_t nn_forward(int n, int64_t nelem, const float *params, float *wt, const float *x0, float *a1, float *a2,
+                      float *out, hipStream_t s)
+{
+    if (nelem <= 0) return hipSuccess;
+    if (n == 3) return forward_t<3>(nelem, params, wt, x0, a1, a2, out, s);
+    if (n == 4) return forward_t<4>(nelem, params, wt, x0, a1, a2, out, s);
+    if (n == 5) return forward_t<5>(nelem, params, wt, x0, a1, a2, out, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t nn_backward(int n, int64_t nelem, const float *params, const float *x0, const float *a1, const float *a2,
+                       const float *gout, float *ga2, float *ga1, float *grads, float *wt, float *partial,
+                       hipStream_t s)
+{
+    if (nelem <= 0) return hipSuccess;
+    if (n == 3) return backward_t<3>(nelem, params, x0, a1, a2, gout, ga2, ga1, grads, wt, partial, s);
+    if (n == 4) return backward_t<4>(nelem, params, x0, a1, a2, gout, ga2, ga1, grads, wt, partial, s);
+    if (n == 5) return backward_t<5>(nelem, params, x0, a1, a2, gout, ga2, ga1, grads, wt, partial, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t nn_input(int n, int64_t nelem, const double *r, const int32_t *emap, const float *logk, float *x0,
+                    float *s, hipStream_t st)
+{
+    if (nelem <= 0) return hipSuccess;
+    if (n == 3) hipLaunchKernelGGL(k_nn_input<3>, dim3(nelem), dim3(128), 0, st, nelem, r, emap, logk, x0, s);
+    else if (n == 4) hipLaunchKernelGGL(k_nn_input<4>, dim3(nelem), dim3(128), 0, st, nelem, r, emap, logk, x0, s);
+    else if (n == 5) hipLaunchKernelGGL(k_nn_input<5>, dim3(nelem), dim3(128), 0, st, nelem, r, emap, logk, x0, s);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t nn_output(int n, int64_t nelem, const float *out, const float *s, const int32_t *emap,
+                     const double *inv_mult, double *z, hipStream_t st)
+{
+    const int P = n * n * n;
+    const int64_t tot = nelem * P;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nn_output, dim3(nblk(tot)), dim3(256), 0, st, tot, P, out, s, emap, inv_mult, z);
+    return hipGetLastError();
+}
+
+hipError_t nn_output_grad(int n, int64_t nelem, const double *gz, const float *s, const int32_t *emap,
+                          const double *inv_mult, float *gout, hipStream_t st)
+{
+    const int P = n * n * n;
+    const int64_t tot = nelem * P;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nn_output_grad, dim3(nblk(tot)), dim3(256), 0, st, tot, P, gz, s, emap, inv_mult, gout);
+    return hipGetLastError();
+}
+
+hipError_t nn_inv_mult(int n, int64_t nelem, int64_t ndof, const int32_t *emap, double *inv_mult, hipStream_t s)
+{
+    const int64_t tot = nelem * n * n * n;
+    hipError_t e = vec_fill(inv_mult, 0.0, ndof, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count, dim3(nblk(tot)), dim3(256), 0, s, tot, emap, inv_mult);
+    hipLaunchKernelGGL(k_recip_or_zero, dim3(nblk(ndof)), dim3(256), 0, s, ndof, inv_mult);
+    return hipGetLastError();
+}
+
+hipError_t nn_adam(float *p, float *g, float *m, float *v, int n, double lr, int step, hipStream_t s)
+{
+    const double bc1 = 1.0 - std::pow(0.9, step), bc2 = 1.0 - std::pow(0.999, step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, s, p, g, m, v, n, (float)lr, (float)bc1, (float)bc2);
+    return hipGetLastError();
+}
+
+hipError_t vec_fill_f32(float *y, float v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)std::min<int64_t>(nblk(n), 8192)), dim3(256), 0, s, y, v, n);
+    return hipGetLastError();
+}
+
+hipError_t vec_sub(double *y, const double *a, const double *b, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sub, dim3((unsigned)std::min<int64_t>(nblk(n), 8192)), dim3(256), 0, s, y, a, b, n);
+    return hipGetLastError();
+}
+hipError_t vec_mul(double *y, const double *a, const double *b, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mul, dim3((unsigned)std::min<int64_t>(nblk(n), 8192)), dim3(256), 0, s, y, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t vec_loss_scale(double *g, int64_t n, double *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loss_scale, dim3((unsigned)std::min<int64_t>(nblk(n), 8192)), dim3(256), 0, s, g, n, sc);
+    return hipGetLastError();
+}
+
+hipError_t coarse_prolong(const BoxDims &b, const double *gll, const double *u1, double *uf, bool add, hipStream_t s)
+{
+    const int64_t nf = ((int64_t)b.nx * b.p + 1) * ((int64_t)b.ny * b.p + 1) * ((int64_t)b.nz * b.p + 1);
+    hipLaunchKernelGGL(k_prolong, dim3(nblk(nf)), dim3(256), 0, s, b, gll, u1, uf, add ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t coarse_restrict(const BoxDims &b, const double *gll, const double *rf, double *r1, hipStream_t s)
+{
+    const int64_t n1 = (int64_t)(b.nx + 1) * (b.ny + 1) * (b.nz + 1);
+    hipLaunchKernelGGL(k_restrict, dim3(nblk(n1)), dim3(256), 0, s, b, gll, rf, r1);
+    return hipGetLastError();
+}
+
+hipError_t coarse_probe_vec(const BoxDims &b, int cls, double *v, hipStream_t s)
+{
+    const int64_t n1 = (int64_t)(b.nx + 1) * (b.ny + 1) * (b.nz + 1);
+    hipLaunchKernelGGL(k_probe_vec, dim3(nblk(n1)), dim3(256), 0, s, b, cls, v);
+    return hipGetLastError();
+}
+
+hipError_t coarse_probe_gather(const BoxDims &b, int cls, const double *y, const uint8_t *ess1, double *S,
+                               hipStream_t s)
+{
+    const int64_t n1 = (int64_t)(b.nx + 1) * (b.ny + 1) * (b.nz + 1);
+    hipLaunchKernelGGL(k_probe_gather, dim3(nblk(n1)), dim3(256), 0, s, b, cls, y, ess1, S);
+    return hipGetLastError();
+}
+
+hipError_t coarse_dinv(int64_t n1, const double *S, double *dinv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dinv_center, dim3(nblk(n1)), dim3(256), 0, s, n1, S, dinv);
+    return hipGetLastError();
+}
+
+hipError_t coarse_pcg(const BoxDims &b, const double *S, const double *dinv, double *r1, double *u, double *z,
+                      double *p0, double *p1, double *Ap, double *partial, CoarseScalars *sc, int iters,
+                      hipStream_t s)
+{
+    const int64_t n1 = (int64_t)(b.nx + 1) * (b.ny + 1) * (b.nz + 1);
+    const unsigned nb = nblk(n1);
+    hipLaunchKernelGGL(k_cpcg_init, dim3(nb), dim3(256), 0, s, n1, dinv, r1, u, z, p0, partial, sc);
+    for (int k = 0; k < iters; ++k) {
+        double *pin = (k & 1) ? p1 : p0, *pout = (k & 1) ? p0 : p1;
+        hipLaunchKernelGGL(k_cpcg_a, dim3(nb), dim3(256), 0, s, b, S, z, pin, pout, Ap, partial, sc);
+        hipLaunchKernelGGL(k_cpcg_b, dim3(nb), dim3(256), 0, s, n1, dinv, pout, Ap, u, r1, z, partial, sc);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hexpa

@@ -193,9 +193,33 @@ __global__ void k_load_scatter(int64_t nelem, int d, int q, const int32_t *__res
     unsafeAtomicAdd(bvec + emap[idx], acc);
 }
 
+// log kappa at every (element, local node), the network's second input channel.
+__global__ void k_logk_tiles(int64_t nelem, int d, const double *__restrict__ vert, const int32_t *__restrict__ hex,
+                             const DevTables *__restrict__ tab, CoeffDev cf, float *__restrict__ out)
+{
+    const int d3 = d * d * d;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nelem * d3) return;
+    const int64_t e = idx / d3;
+    const int I = (int)(idx - e * d3);
+    Hex h;
+    load_hex(vert, hex, e, h);
+    double x[3], J[3][3];
+    map_point(h, tab->nodes[I % d], tab->nodes[(I / d) % d], tab->nodes[I / (d * d)], x, J);
+    out[idx] = (float)log(coeff_eval(cf, x));
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
+
+hipError_t logk_tiles(const pa_op *op, float *out, hipStream_t s)
+{
+    const int64_t n = (int64_t)op->nelem * op->d * op->d * op->d;
+    hipLaunchKernelGGL(k_logk_tiles, dim3(nblk(n)), dim3(256), 0, s, (int64_t)op->nelem, op->d, op->d_vert,
+                       op->d_hex, op->d_tab, op->coeff, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_setup_qdata(const pa_op *op, const CoeffDev &cf, int *d_bad, hipStream_t s)
 {

@@ -34,4 +34,12 @@ template <class T>
 hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
                      double *hist, int it, hipStream_t s);
 
+// ------------------------------------------------------------------ FCG vectors
+// x += alpha p; rold = r; r -= alpha Ap; hist[2 it] = r.r, hist[2 it + 1] = breakdown
+hipError_t fcg_update(double *x, double *r, double *rold, const double *p, const double *Ap, int64_t n,
+                      double *partial, CgScalars *sc, double *hist, int it, hipStream_t s);
+// beta = (z.(r - rold)) / rz, rz = z.r (rold == nullptr: beta = 0, first direction), p = z + beta p
+hipError_t fcg_direction(const double *z, const double *r, const double *rold, double *p, int64_t n, double *partial,
+                         CgScalars *sc, hipStream_t s);
+
 }  // namespace hexpa

@@ -232,6 +232,85 @@ __global__ void k_axpy_f32(double *x, double a, const float *d, int64_t n)
         x[i] = fma(a, (double)d[i], x[i]);
 }
 
+// ---- flexible CG (FCG(1)) pieces
+// x += alpha p; rold = r; r -= alpha Ap; partial sums of r.r
+__global__ void k_fcg_update(double *__restrict__ x, double *__restrict__ r, double *__restrict__ rold,
+                             const double *__restrict__ p, const double *__restrict__ Ap, int64_t n,
+                             const CgScalars *__restrict__ s, double *partial)
+{
+    __shared__ double sh[256];
+    const double alpha = s->alpha;
+    double v[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = r[i];
+        rold[i] = ri;
+        const double rn = fma(-alpha, Ap[i], ri);
+        r[i] = rn;
+        v[0] = fma(rn, rn, v[0]);
+    }
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+__global__ void k_fcg_rr(const double *partial, int nb, CgScalars *s, double *rr_hist, int it)
+{
+    __shared__ double sh[256];
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < nb; i += 256) v[0] += partial[i];
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) {
+        if (!isfinite(v[0])) s->breakdown = 1;
+        s->rr = v[0];
+        rr_hist[2 * it] = v[0];
+        rr_hist[2 * it + 1] = (double)s->breakdown;
+    }
+}
+
+// partial sums of z.r and z.rold (rold may be null)
+__global__ void k_fcg_dots(const double *__restrict__ z, const double *__restrict__ r, const double *__restrict__ rold,
+                           int64_t n, double *partial)
+{
+    __shared__ double sh[2 * 256];
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        v[0] = fma(z[i], r[i], v[0]);
+        if (rold) v[1] = fma(z[i], rold[i], v[1]);
+    }
+    block_sum<2>(v, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = v[0];
+        partial[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+// beta = (z.r - z.rold) / rz (0 for the first direction); rz = z.r
+__global__ void k_fcg_beta(const double *partial, int nb, int first, CgScalars *s)
+{
+    __shared__ double sh[2 * 256];
+    double v[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        v[0] += partial[2 * i];
+        v[1] += partial[2 * i + 1];
+    }
+    block_sum<2>(v, sh);
+    if (threadIdx.x == 0) {
+        const double zr = v[0], zro = v[1];
+        if (!isfinite(zr) || !isfinite(zro)) s->breakdown = 1;
+        s->beta = (first || s->rz == 0.0) ? 0.0 : (zr - zro) / s->rz;
+        s->rz = zr;
+    }
+}
+
+// p = z + beta p (p = z for the first direction)
+__global__ void k_fcg_p(double *__restrict__ p, const double *__restrict__ z, int64_t n, int first,
+                        const CgScalars *__restrict__ s)
+{
+    const double beta = s->beta;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = first ? z[i] : fma(beta, p[i], z[i]);
+}
+
 }  // namespace
 
 template <class T>
@@ -332,5 +411,23 @@ hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, do
                                      double *, int, hipStream_t);
 HEXPA_INST(double)
 HEXPA_INST(float)
+
+hipError_t fcg_update(double *x, double *r, double *rold, const double *p, const double *Ap, int64_t n,
+                      double *partial, CgScalars *sc, double *hist, int it, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fcg_update, dim3(kRedBlocks), dim3(256), 0, s, x, r, rold, p, Ap, n, sc, partial);
+    hipLaunchKernelGGL(k_fcg_rr, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc, hist, it);
+    return hipGetLastError();
+}
+
+hipError_t fcg_direction(const double *z, const double *r, const double *rold, double *p, int64_t n, double *partial,
+                         CgScalars *sc, hipStream_t s)
+{
+    const int first = rold ? 0 : 1;
+    hipLaunchKernelGGL(k_fcg_dots, dim3(kRedBlocks), dim3(256), 0, s, z, r, rold, n, partial);
+    hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(256), 0, s, partial, kRedBlocks, first, sc);
+    hipLaunchKernelGGL(k_fcg_p, dim3(kRedBlocks), dim3(256), 0, s, p, z, n, first, sc);
+    return hipGetLastError();
+}
 
 }  // namespace hexpa

@@ -20,13 +20,17 @@ PA_ERR_NOT_CONVERGED, PA_ERR_BREAKDOWN, PA_ERR_IO = -5, -6, -7
 PA_MASS, PA_DIFFUSION = 1, 2
 PA_COEFF_CONST, PA_COEFF_SINE, PA_COEFF_GRID = 0, 1, 2
 PA_VARIANT_MFMA, PA_VARIANT_VALU, PA_VARIANT_MFMA_COLORED = 0, 1, 2
-PA_CG_PLAIN, PA_CG_JACOBI, PA_CG_MIXED_IR = 0, 1, 2
+PA_CG_PLAIN, PA_CG_JACOBI, PA_CG_MIXED_IR, PA_CG_FCG = 0, 1, 2, 3
+PA_LP_LOSS_ENERGY, PA_LP_LOSS_L2 = 0, 1
 PA_LP_FP16, PA_LP_BF16 = 0, 1
 
 # every symbol include/hexpa.h declares
 EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_lp", "pa_apply_constrained", "pa_diag", "pa_load", "pa_qpoints", "pa_nodes",
            "pa_get_elem_dofs", "pa_get_ess", "pa_set_variant", "pa_info", "pa_destroy", "pa_last_error",
-           "cg_solve", "pa_debug_mfma_f64", "pa_debug_mfma16")
+           "cg_solve", "pa_debug_mfma_f64", "pa_debug_mfma16",
+           "pa_lp_create", "pa_lp_bind", "pa_lp_configure", "pa_lp_num_params", "pa_lp_get_params",
+           "pa_lp_set_params", "pa_lp_logk", "pa_lp_apply", "pa_lp_coarse", "pa_lp_net", "pa_lp_loss_grad",
+           "pa_lp_train_step", "pa_lp_save", "pa_lp_load", "pa_lp_destroy")
 
 
 class HexpaError(RuntimeError):
@@ -57,13 +61,21 @@ class Info(ctypes.Structure):
 class CgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_it", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("constrained", ctypes.c_int32), ("lp_fmt", ctypes.c_int32),
-                ("inner_max", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+                ("inner_max", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("lp", ctypes.c_void_p),
+                ("n_capture", ctypes.c_int32), ("pad_", ctypes.c_int32), ("capture_at", ctypes.c_void_p),
+                ("capture_x", ctypes.c_void_p)]
 
 
 class CgResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res_recursive", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("inner_iters_total", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("inner_iters_total", ctypes.c_int32), ("fallback", ctypes.c_int32)]
+
+
+class LpOpts(ctypes.Structure):
+    _fields_ = [("use_net", ctypes.c_int32), ("use_coarse", ctypes.c_int32), ("coarse_iters", ctypes.c_int32),
+                ("loss", ctypes.c_int32), ("seed", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("lr", ctypes.c_double)]
 
 
 def _load():
@@ -90,6 +102,20 @@ def _load():
         "cg_solve": [vp, vp, vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgResult), vp],
         "pa_debug_mfma_f64": [i32, vp, vp, vp, vp],
         "pa_debug_mfma16": [i32, vp, vp, vp, vp],
+        "pa_lp_create": [vp, ctypes.POINTER(LpOpts), ctypes.POINTER(vp)],
+        "pa_lp_bind": [vp, vp],
+        "pa_lp_configure": [vp, ctypes.POINTER(LpOpts)],
+        "pa_lp_num_params": [],
+        "pa_lp_get_params": [vp, vp, i32],
+        "pa_lp_set_params": [vp, vp, i32],
+        "pa_lp_logk": [vp, vp],
+        "pa_lp_apply": [vp, vp, vp, vp],
+        "pa_lp_coarse": [vp, vp, vp, vp],
+        "pa_lp_net": [vp, vp, vp, vp],
+        "pa_lp_loss_grad": [vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp],
+        "pa_lp_train_step": [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp],
+        "pa_lp_save": [vp, ctypes.c_char_p],
+        "pa_lp_load": [vp, ctypes.c_char_p],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -97,6 +123,8 @@ def _load():
         fn.restype = ctypes.c_int
     lib.pa_destroy.argtypes = [vp]
     lib.pa_destroy.restype = None
+    lib.pa_lp_destroy.argtypes = [vp]
+    lib.pa_lp_destroy.restype = None
     lib.pa_last_error.argtypes = []
     lib.pa_last_error.restype = ctypes.c_char_p
     return lib
@@ -238,15 +266,103 @@ def pa_destroy(h):
 
 
 def cg_solve(h, b, x, rtol=1e-8, max_it=10000, mode=PA_CG_JACOBI, check_every=1, constrained=True,
-             lp_fmt=PA_LP_FP16, inner_max=200, inner_rtol=1e-2, stream=None, raise_on_fail=True):
+             lp_fmt=PA_LP_FP16, inner_max=200, inner_rtol=1e-2, lp=None, capture_at=None, capture_x=None,
+             stream=None, raise_on_fail=True):
+    """capture_at: ascending iteration numbers whose iterates are copied into the rows of the
+    device tensor capture_x [len(capture_at)][ndof] (Jacobi-PCG only)."""
+    cap = None
     o = CgOpts(float(rtol), int(max_it), int(mode), int(check_every), int(bool(constrained)), int(lp_fmt),
-               int(inner_max), float(inner_rtol))
+               int(inner_max), float(inner_rtol), None if lp is None else (lp.value if isinstance(lp, ctypes.c_void_p) else int(lp)), 0, 0, None,
+               None)
+    if capture_at is not None:
+        cap = np.ascontiguousarray(capture_at, dtype=np.int32)
+        o.n_capture = cap.size
+        o.capture_at = cap.ctypes.data
+        o.capture_x = _dptr(capture_x, n=cap.size * b.numel())
     r = CgResult()
     rc = _lib.cg_solve(h, _dptr(b), _dptr(x), ctypes.byref(o), ctypes.byref(r), _stream(stream))
     if raise_on_fail:
         _check(rc)
     return {"rc": rc, "iters": r.iters, "status": r.status, "rel_res_recursive": r.rel_res_recursive,
-            "rel_res_true": r.rel_res_true, "seconds": r.seconds, "inner_iters_total": r.inner_iters_total}
+            "rel_res_true": r.rel_res_true, "seconds": r.seconds, "inner_iters_total": r.inner_iters_total,
+            "fallback": r.fallback}
+
+
+def _lp_opts(use_net=True, use_coarse=True, coarse_iters=20, loss=PA_LP_LOSS_ENERGY, seed=0, lr=1e-3):
+    return LpOpts(int(bool(use_net)), int(bool(use_coarse)), int(coarse_iters), int(loss), int(seed), 0, float(lr))
+
+
+def pa_lp_create(h, **opts):
+    out = ctypes.c_void_p()
+    _check(_lib.pa_lp_create(h, ctypes.byref(_lp_opts(**opts)), ctypes.byref(out)))
+    return out
+
+
+def pa_lp_bind(lp, h):
+    _check(_lib.pa_lp_bind(lp, h))
+
+
+def pa_lp_configure(lp, **opts):
+    _check(_lib.pa_lp_configure(lp, ctypes.byref(_lp_opts(**opts))))
+
+
+def pa_lp_num_params():
+    return _lib.pa_lp_num_params()
+
+
+def pa_lp_get_params(lp):
+    n = pa_lp_num_params()
+    out = np.zeros(n, dtype=np.float32)
+    _check(_lib.pa_lp_get_params(lp, out.ctypes.data, n))
+    return out
+
+
+def pa_lp_set_params(lp, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_lib.pa_lp_set_params(lp, p.ctypes.data, p.size))
+
+
+def pa_lp_logk(lp, out):
+    _check(_lib.pa_lp_logk(lp, _dptr(out)))
+
+
+def pa_lp_apply(lp, r, z, stream=None):
+    _check(_lib.pa_lp_apply(lp, _dptr(r), _dptr(z), _stream(stream)))
+
+
+def pa_lp_coarse(lp, r, z, stream=None):
+    _check(_lib.pa_lp_coarse(lp, _dptr(r), _dptr(z), _stream(stream)))
+
+
+def pa_lp_net(lp, r, z, stream=None):
+    _check(_lib.pa_lp_net(lp, _dptr(r), _dptr(z), _stream(stream)))
+
+
+def pa_lp_loss_grad(lp, r, t, want_grad=True, stream=None):
+    loss = ctypes.c_double()
+    g = np.zeros(pa_lp_num_params(), dtype=np.float32) if want_grad else None
+    _check(_lib.pa_lp_loss_grad(lp, _dptr(r), _dptr(t), ctypes.byref(loss), None if g is None else g.ctypes.data,
+                                _stream(stream)))
+    return loss.value, g
+
+
+def pa_lp_train_step(lp, b, xstar, xk, want_loss=True, stream=None):
+    loss = ctypes.c_double()
+    _check(_lib.pa_lp_train_step(lp, _dptr(b), _dptr(xstar), _dptr(xk), ctypes.byref(loss) if want_loss else None,
+                                 _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def pa_lp_save(lp, path):
+    _check(_lib.pa_lp_save(lp, os.fsencode(path)))
+
+
+def pa_lp_load(lp, path):
+    _check(_lib.pa_lp_load(lp, os.fsencode(path)))
+
+
+def pa_lp_destroy(lp):
+    _lib.pa_lp_destroy(lp)
 
 
 def pa_debug_mfma_f64(shape, A, B, D, stream=None):
@@ -321,6 +437,72 @@ class PAOperator:
     def close(self):
         if self.h:
             pa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LearnedPreconditioner:
+    """Owns a pa_lp handle bound to a PAOperator (thin convenience over the pa_lp_* calls)."""
+
+    def __init__(self, op, **opts):
+        self.op = op
+        self.h = pa_lp_create(op.h, **opts)
+
+    def bind(self, op):
+        pa_lp_bind(self.h, op.h)
+        self.op = op
+
+    def configure(self, **opts):
+        pa_lp_configure(self.h, **opts)
+
+    def params(self):
+        return pa_lp_get_params(self.h)
+
+    def set_params(self, p):
+        pa_lp_set_params(self.h, p)
+
+    def apply(self, r, z=None):
+        z = self.op._vec() if z is None else z
+        pa_lp_apply(self.h, r, z)
+        return z
+
+    def coarse(self, r, z=None):
+        z = self.op._vec() if z is None else z
+        pa_lp_coarse(self.h, r, z)
+        return z
+
+    def net(self, r, z=None):
+        z = self.op._vec() if z is None else z
+        pa_lp_net(self.h, r, z)
+        return z
+
+    def logk(self):
+        import torch
+        d = self.op.p + 1
+        out = torch.empty(self.op.nelem * d ** 3, dtype=torch.float32, device="cuda")
+        pa_lp_logk(self.h, out)
+        return out
+
+    def loss_grad(self, r, t):
+        return pa_lp_loss_grad(self.h, r, t)
+
+    def train_step(self, b, xstar, xk, want_loss=True):
+        return pa_lp_train_step(self.h, b, xstar, xk, want_loss)
+
+    def save(self, path):
+        pa_lp_save(self.h, path)
+
+    def load(self, path):
+        pa_lp_load(self.h, path)
+
+    def close(self):
+        if self.h:
+            pa_lp_destroy(self.h)
             self.h = None
 
     def __del__(self):

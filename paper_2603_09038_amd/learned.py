@@ -1,0 +1,103 @@
+"""Training and evaluation of the learned two-level preconditioner (orchestration only).
+
+Every numerical step runs in the library: the Jacobi-PCG that produces the training
+iterates (cg_solve with iterate capture), the residuals and targets, the network's
+forward and backward passes and Adam (pa_lp_train_step), and the FCG solves that compare
+the preconditioners.  This module only chooses coefficient draws, builds operators and
+loops over them.
+
+Training data (per draw d): the system A_c x = b_c with a known solution x*_d, b_c =
+A_c x*_d, solved by FP64 Jacobi-PCG from 0; the iterates x_k at roughly log-spaced k give
+pairs (r_k = b_c - A_c x_k, e_k = x*_d - x_k) with the exact error known without a tight
+solve.  The network part is trained on the target e_k minus the coarse correction of r_k.
+"""
+import time
+
+import numpy as np
+
+from . import hexpa
+
+# roughly log-spaced iteration numbers (Fibonacci-like), 0 = the first residual b
+CAPTURE_AT = (0, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89, 144, 233, 377, 610, 987, 1597)
+
+
+def lognormal_operator(mesh, n, p, draw, sigma=1.0, ell=0.1, nfft=128):
+    """PA diffusion operator (Q = p + 2, Dirichlet box boundary) with kappa = exp(sigma g_draw)."""
+    import synth
+    grid, contrast = synth.lognormal_kappa_grid(draw, sigma=sigma, ell=ell, nfft=nfft)
+    op = hexpa.PAOperator(mesh, p, p + 2, coeff={"kind": hexpa.PA_COEFF_GRID, "grid": grid},
+                          ops=hexpa.PA_DIFFUSION, ess_mode=1)
+    op.contrast = contrast
+    return op
+
+
+def capture_iterates(op, xstar, max_it=1600, capture_at=CAPTURE_AT):
+    """b = A_c x*, and the Jacobi-PCG iterates x_k at the listed k that the solve reaches."""
+    import torch
+    b = op.apply_constrained(xstar)
+    cap = torch.empty((len(capture_at), op.ndof), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    res = hexpa.cg_solve(op.h, b, x, rtol=1e-10, max_it=max_it, mode=hexpa.PA_CG_JACOBI, capture_at=capture_at,
+                         capture_x=cap, check_every=8, raise_on_fail=False)
+    reached = [j for j, k in enumerate(capture_at) if k <= res["iters"]]
+    return b, cap[reached], res
+
+
+def train(lp, mesh, n, p, draws, epochs=1, seed=0, sigma=1.0, log=None):
+    """Train lp's network on the iterates of the given coefficient draws (one operator
+    at a time).  Returns per-step losses and the seconds spent (capture and training)."""
+    import synth
+    import torch
+    rng = np.random.default_rng([seed, 11])
+    losses, t_capture, t_train = [], 0.0, 0.0
+    for ep in range(epochs):
+        for d in draws:
+            t0 = time.perf_counter()
+            op = lognormal_operator(mesh, n, p, d, sigma=sigma)
+            xstar = torch.tensor(synth.train_solution(op.nodes().cpu().numpy(), d), dtype=torch.float64,
+                                 device="cuda")
+            b, xs, _ = capture_iterates(op, xstar)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            lp.bind(op)
+            for j in rng.permutation(xs.shape[0]):
+                losses.append(lp.train_step(b, xstar, xs[j]))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            t_capture += t1 - t0
+            t_train += t2 - t1
+            if log:
+                log(f"epoch {ep} draw {d}: {xs.shape[0]} pairs, mean loss {np.mean(losses[-xs.shape[0]:]):.4f}")
+    return losses, t_capture, t_train
+
+
+def compare(lp, mesh, n, p, draws, rtol=1e-8, sigma=1.0, coarse_iters=None, max_it=20000, log=None):
+    """Iterations and seconds to rtol on held-out draws for (i) Jacobi-PCG, (ii) FCG with
+    Jacobi + coarse correction (the preconditioner without the network), (iii) FCG with
+    network + coarse correction.  The right-hand side is b = A_c x* with x* the nodal
+    interpolant of sin(pi x) sin(pi y) sin(pi z)."""
+    import synth
+    import torch
+    rows = []
+    for d in draws:
+        op = lognormal_operator(mesh, n, p, d, sigma=sigma)
+        xstar = torch.tensor(synth.u_manufactured(op.nodes().cpu().numpy()), dtype=torch.float64, device="cuda")
+        b = op.apply_constrained(xstar)
+        lp.bind(op)
+        row = {"draw": d, "contrast": op.contrast}
+        x = torch.zeros_like(b)
+        row["jacobi"] = hexpa.cg_solve(op.h, b, x, rtol=rtol, max_it=max_it, mode=hexpa.PA_CG_JACOBI,
+                                       check_every=8, raise_on_fail=False)
+        for key, use_net in (("coarse_jacobi", False), ("coarse_net", True)):
+            kw = {} if coarse_iters is None else {"coarse_iters": coarse_iters}
+            lp.configure(use_net=use_net, use_coarse=True, **kw)
+            x = torch.zeros_like(b)
+            row[key] = hexpa.cg_solve(op.h, b, x, rtol=rtol, max_it=max_it, mode=hexpa.PA_CG_FCG, lp=lp.h,
+                                      check_every=4, raise_on_fail=False)
+        rows.append(row)
+        if log:
+            log("draw %d: jacobi %d it %.3fs | fcg coarse+jacobi %d it %.3fs | fcg coarse+net %d it %.3fs%s" % (
+                d, row["jacobi"]["iters"], row["jacobi"]["seconds"], row["coarse_jacobi"]["iters"],
+                row["coarse_jacobi"]["seconds"], row["coarse_net"]["iters"], row["coarse_net"]["seconds"],
+                " (fallback)" if row["coarse_net"]["fallback"] else ""))
+    return rows

@@ -61,3 +61,17 @@ def test_bad_arguments_are_rejected_without_a_device(lib):
     assert lib.pa_diag(None, None, 0, None) == hexpa.PA_ERR_ARG
     assert lib.cg_solve(None, None, None, None, None, None) == hexpa.PA_ERR_ARG
     assert lib.pa_set_variant(None, 0) == hexpa.PA_ERR_ARG
+
+
+def test_learned_preconditioner_rejects_bad_arguments_without_a_device(lib):
+    from paper_2603_09038_amd import hexpa
+    out = ctypes.c_void_p()
+    o = hexpa._lp_opts()
+    assert lib.pa_lp_create(None, ctypes.byref(o), ctypes.byref(out)) == hexpa.PA_ERR_ARG
+    assert lib.pa_lp_create(None, ctypes.byref(o), None) == hexpa.PA_ERR_ARG
+    assert lib.pa_lp_apply(None, None, None, None) == hexpa.PA_ERR_ARG
+    assert lib.pa_lp_load(None, b"/nonexistent") == hexpa.PA_ERR_ARG
+    assert lib.pa_lp_num_params() == 16 * 2 * 27 + 16 + 16 * 16 * 27 + 16 + 16 * 27 + 1
+    bad = hexpa._lp_opts(coarse_iters=0)
+    assert lib.pa_lp_configure(None, ctypes.byref(bad)) == hexpa.PA_ERR_ARG
+

@@ -1,0 +1,242 @@
+"""Learned two-level preconditioner on MI355X against the CPU oracle.
+
+Bars.  The network runs in FP32 (weights and activations) on FP64 vectors; its input is
+the FP64 residual divided by the element RMS, rounded once to FP32, and each of the three
+layers sums at most 16 * 27 = 432 products.  With unit roundoff u = 2^-24 the normwise
+error of the network output is a few hundred u times the condition of the layers'
+sums; the bound used is 2e-5 (relative, normwise) for outputs and 1e-4 per parameter
+block for gradients (the weight gradients sum over every element and node).  The coarse
+level is FP64 throughout: 1e-10.  Adam's first step moves every parameter with a
+non-negligible gradient by lr * sign(g); the test compares those moves.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import nn, solvers
+from oracle.coarse import CoarseLevel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hx():
+    import torch  # noqa: F401
+    from paper_2603_09038_amd import hexpa
+    return hexpa
+
+
+def _t(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _problem(hx, n, p, seed=0, sigma=1.0, ops=2):
+    mesh = synth.box_mesh(n, perturb=0.1, seed=seed)
+    grid, _ = synth.lognormal_kappa_grid(seed, sigma=sigma, ell=0.1, nfft=32)
+    op = hx.PAOperator(mesh, p, p + 2, coeff={"kind": hx.PA_COEFF_GRID, "grid": grid}, ops=ops, ess_mode=1)
+    coeff = oracle.Coeff.from_grid(grid)
+    P = oracle.Problem(mesh, p, p + 2, coeff=coeff,
+                       ops=(oracle.MASS if ops & 1 else 0) | (oracle.DIFFUSION if ops & 2 else 0))
+    ess = oracle.box_boundary(n, p).astype(bool)
+    return mesh, grid, coeff, op, P, ess
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _oracle_logk(P, coeff):
+    return np.log(coeff.at(P.nodes()))[P.elem_dofs]
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_logk_tiles_and_network_forward(hx, p):
+    n = {2: 4, 3: 3, 4: 3}[p]
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=p)
+    lp = hx.LearnedPreconditioner(op, use_net=True, use_coarse=False)
+    logk = lp.logk().cpu().numpy().reshape(P.elem_dofs.shape)
+    ref = _oracle_logk(P, coeff)
+    np.testing.assert_allclose(logk, ref, rtol=0, atol=2e-6 * max(1.0, np.abs(ref).max()))
+    ps = synth.net_params(2, 16, seed=10 + p)
+    lp.set_params(synth.flat_params(ps))
+    np.testing.assert_array_equal(lp.params(), synth.flat_params(ps))
+    r = np.where(ess, 0.0, synth.rand_x(op.ndof, 3))
+    z = lp.net(_t(r)).cpu().numpy()
+    zr, _ = nn.precond_nn(nn.Net(ps), r, ref, P.elem_dofs, p + 1, op.ndof, ess)
+    assert _rel(z, zr) <= 2e-5, _rel(z, zr)
+    assert np.all(z[ess] == 0.0)
+    # positive 1-homogeneity survives the FP32 network: scaling by 2^k is exact
+    z4 = lp.net(_t(4.0 * r)).cpu().numpy()
+    np.testing.assert_allclose(z4, 4.0 * z, rtol=1e-6, atol=1e-12 * np.abs(z).max())
+    lp.close()
+    op.close()
+
+
+@pytest.mark.parametrize("p,loss", [(2, 0), (4, 0), (4, 1), (3, 1)])
+def test_loss_and_gradient(hx, p, loss):
+    n = 3
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=20 + p)
+    lp = hx.LearnedPreconditioner(op, use_net=True, use_coarse=False, loss=loss)
+    ps = synth.net_params(2, 16, seed=30 + p)
+    lp.set_params(synth.flat_params(ps))
+    r = np.where(ess, 0.0, synth.rand_x(op.ndof, 4))
+    t = np.where(ess, 0.0, synth.rand_x(op.ndof, 5))
+    L, g = lp.loss_grad(_t(r), _t(t))
+    Amul = solvers.constrained(P.apply, ess) if loss == 0 else None
+    Lr, gr = nn.loss_and_grads(nn.Net(ps), r, t, _oracle_logk(P, coeff), P.elem_dofs, p + 1, op.ndof, ess, Amul=Amul)
+    assert abs(L - Lr) <= 2e-5 * abs(Lr), (L, Lr)
+    off = 0
+    for k, gref in enumerate(gr):
+        blk = g[off:off + gref.size]
+        off += gref.size
+        assert _rel(blk, gref.ravel()) <= 1e-4, (k, _rel(blk, gref.ravel()))
+    assert off == g.size
+    lp.close()
+    op.close()
+
+
+def test_adam_step_matches_the_oracle(hx):
+    n, p = 3, 2
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=40)
+    lp = hx.LearnedPreconditioner(op, use_net=True, use_coarse=False, loss=1, lr=1e-2)
+    ps = synth.net_params(2, 16, seed=41)
+    lp.set_params(synth.flat_params(ps))
+    Ac = solvers.constrained(P.apply, ess)
+    xstar = np.where(ess, 0.0, synth.rand_x(op.ndof, 6))
+    b = Ac(xstar)
+    xk = np.where(ess, b, 0.3 * synth.rand_x(op.ndof, 7))
+    lp.train_step(_t(b), _t(xstar), _t(xk))
+    after = lp.params()
+    r = b - Ac(xk)
+    t = np.where(ess, 0.0, xstar - xk)
+    _, gr = nn.loss_and_grads(nn.Net(ps), r, t, _oracle_logk(P, coeff), P.elem_dofs, p + 1, op.ndof, ess)
+    g = np.concatenate([q.ravel() for q in gr])
+    p0 = synth.flat_params(ps).astype(np.float64)
+    m, v = [np.zeros_like(g)], [np.zeros_like(g)]
+    ref = nn.adam_step([p0], [g], m, v, 1, lr=1e-2)[0]
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert big.sum() > 0.5 * g.size
+    np.testing.assert_allclose(after[big], ref[big], rtol=0, atol=1e-5)
+    lp.close()
+    op.close()
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_coarse_correction(hx, p):
+    n = 4
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=50 + p)
+    lp = hx.LearnedPreconditioner(op, use_net=False, use_coarse=True, coarse_iters=12)
+    r = np.where(ess, 0.0, synth.rand_x(op.ndof, 8))
+    z = lp.coarse(_t(r)).cpu().numpy()
+    cl = CoarseLevel(mesh, n, p, coeff)
+    zr = cl.correction(r, 12)
+    assert _rel(z, zr) <= 1e-10, _rel(z, zr)
+    # the full preconditioner with the network switched off: Jacobi + coarse
+    zf = lp.apply(_t(r)).cpu().numpy()
+    dinv = 1.0 / solvers.constrained_diag(P.diag(), ess)
+    ref = np.where(ess, 0.0, dinv * r) + zr
+    assert _rel(zf, ref) <= 1e-10, _rel(zf, ref)
+    lp.close()
+    op.close()
+
+
+def test_full_preconditioner_with_network(hx):
+    n, p = 4, 4
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=60)
+    lp = hx.LearnedPreconditioner(op, use_net=True, use_coarse=True, coarse_iters=8)
+    ps = synth.net_params(2, 16, seed=61)
+    lp.set_params(synth.flat_params(ps))
+    r = np.where(ess, 0.0, synth.rand_x(op.ndof, 9))
+    z = lp.apply(_t(r)).cpu().numpy()
+    zn, _ = nn.precond_nn(nn.Net(ps), r, _oracle_logk(P, coeff), P.elem_dofs, p + 1, op.ndof, ess)
+    zc = CoarseLevel(mesh, n, p, coeff).correction(r, 8)
+    assert _rel(z, zn + zc) <= 2e-5
+    lp.close()
+    op.close()
+
+
+def test_fcg_with_jacobi_reproduces_pcg(hx):
+    """A fixed SPD preconditioner makes FCG(1) and PCG the same method in exact arithmetic."""
+    n, p = 5, 4
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=70)
+    xs = synth.u_manufactured(op.nodes().cpu().numpy())
+    b = op.apply_constrained(_t(xs))
+    import torch
+    x1 = torch.zeros_like(b)
+    r1 = hx.cg_solve(op.h, b, x1, rtol=1e-9, max_it=5000, mode=hx.PA_CG_JACOBI)
+    lp = hx.LearnedPreconditioner(op, use_net=False, use_coarse=False)
+    x2 = torch.zeros_like(b)
+    r2 = hx.cg_solve(op.h, b, x2, rtol=1e-9, max_it=5000, mode=hx.PA_CG_FCG, lp=lp.h)
+    assert r2["rc"] == 0 and r2["fallback"] == 0
+    assert abs(r1["iters"] - r2["iters"]) <= max(2, 0.02 * r1["iters"]), (r1, r2)
+    assert _rel(x2.cpu().numpy(), x1.cpu().numpy()) <= 1e-7
+    lp.close()
+    op.close()
+
+
+@pytest.mark.parametrize("use_net", [False])
+def test_fcg_two_level_converges(hx, use_net):
+    n, p = 5, 4
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=80)
+    xs = synth.u_manufactured(op.nodes().cpu().numpy())
+    b = op.apply_constrained(_t(xs))
+    import torch
+    lp = hx.LearnedPreconditioner(op, use_net=use_net, use_coarse=True, coarse_iters=20, seed=3)
+    x = torch.zeros_like(b)
+    res = hx.cg_solve(op.h, b, x, rtol=1e-8, max_it=3000, mode=hx.PA_CG_FCG, lp=lp.h)
+    assert res["rc"] == 0 and res["rel_res_true"] <= 1e-8, res
+    Ac = solvers.constrained(P.apply, ess)
+    bb, xx = b.cpu().numpy(), x.cpu().numpy()
+    assert np.linalg.norm(bb - Ac(xx)) <= 1.05e-8 * np.linalg.norm(bb)
+    x0 = torch.zeros_like(b)
+    rj = hx.cg_solve(op.h, b, x0, rtol=1e-8, max_it=5000, mode=hx.PA_CG_JACOBI)
+    if not use_net:
+        # the coarse correction must pay in iterations over Jacobi alone
+        assert res["iters"] < rj["iters"], (res, rj)
+    lp.close()
+    op.close()
+
+
+def test_capture_of_pcg_iterates(hx):
+    import torch
+    n, p = 4, 2
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=90)
+    xs = synth.u_manufactured(op.nodes().cpu().numpy())
+    b = op.apply_constrained(_t(xs))
+    at = [0, 1, 5, 12]
+    cap = torch.full((len(at), op.ndof), float("nan"), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    hx.cg_solve(op.h, b, x, rtol=1e-12, max_it=40, mode=hx.PA_CG_JACOBI, capture_at=at, capture_x=cap,
+                raise_on_fail=False)
+    cap = cap.cpu().numpy()
+    assert np.all(cap[0] == np.where(ess, b.cpu().numpy(), 0.0))
+    for j, k in enumerate(at[1:], start=1):
+        xk = torch.zeros_like(b)
+        hx.cg_solve(op.h, b, xk, rtol=1e-30, max_it=k, mode=hx.PA_CG_JACOBI, raise_on_fail=False)
+        assert _rel(cap[j], xk.cpu().numpy()) <= 1e-12, k
+    op.close()
+
+
+def test_parameter_file_roundtrip(hx, tmp_path):
+    n, p = 3, 2
+    mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=95)
+    lp = hx.LearnedPreconditioner(op, use_net=True, use_coarse=False)
+    ps = synth.flat_params(synth.net_params(2, 16, seed=96))
+    lp.set_params(ps)
+    f = tmp_path / "w.bin"
+    lp.save(str(f))
+    lp.set_params(np.zeros_like(ps))
+    lp.load(str(f))
+    np.testing.assert_array_equal(lp.params(), ps)
+    raw = bytearray(f.read_bytes())
+    raw[40] ^= 0x01
+    g = tmp_path / "bad.bin"
+    g.write_bytes(bytes(raw))
+    with pytest.raises(hx.HexpaError) as ei:
+        lp.load(str(g))
+    assert ei.value.code == hx.PA_ERR_IO
+    np.testing.assert_array_equal(lp.params(), ps)
+    lp.close()
+    op.close()
