@@ -175,6 +175,40 @@ def run_mixed(hexpa, n=32, p=6, q=8):
     return out
 
 
+def run_learned(hexpa, ntrain, nheld, n=32, p=4, weights=None):
+    """Learned two-level preconditioner: train on log-normal draws 0..ntrain-1 (iterates of
+    Jacobi-PCG on b = A_c x*_d), then on held-out draws 200.. compare FP64 Jacobi-PCG,
+    FCG with coarse correction + Jacobi ("without the network") and FCG with coarse
+    correction + network, each to 1e-8 from x = 0."""
+    import synth
+    from paper_2603_09038_amd import learned
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    op0 = learned.lognormal_operator(mesh, n, p, 0)
+    lp = hexpa.LearnedPreconditioner(op0, use_net=True, use_coarse=True, coarse_iters=20, lr=1e-3)
+    out = {"workload": f"{n}^3 perturbed hex mesh, p={p}, Q={p + 2}, log-normal kappa draws, Dirichlet",
+           "ndof": op0.ndof, "train_draws": ntrain, "held_out_draws": nheld}
+    if weights and os.path.exists(weights):
+        lp.load(weights)
+        out["weights"] = "loaded"
+    else:
+        losses, tc, tt = learned.train(lp, mesh, n, p, list(range(ntrain)), log=log)
+        out.update({"train_steps": len(losses), "train_seconds": tt, "capture_seconds": tc,
+                    "loss_first": float(np.mean(losses[:16])), "loss_last": float(np.mean(losses[-16:]))})
+    rows = learned.compare(lp, mesh, n, p, list(range(200, 200 + nheld)), log=log)
+    for key in ("jacobi", "coarse_jacobi", "coarse_net"):
+        out[key] = {"iters": [r[key]["iters"] for r in rows], "seconds": [r[key]["seconds"] for r in rows],
+                    "rel_res_true": [r[key]["rel_res_true"] for r in rows],
+                    "status": [r[key]["rc"] for r in rows]}
+        out[key]["seconds_mean"] = float(np.mean(out[key]["seconds"]))
+        out[key]["iters_mean"] = float(np.mean(out[key]["iters"]))
+    out["fallbacks"] = sum(r["coarse_net"]["fallback"] for r in rows)
+    out["contrast"] = [r["contrast"] for r in rows]
+    out["speedup_net_vs_jacobi"] = out["jacobi"]["seconds_mean"] / out["coarse_net"]["seconds_mean"]
+    out["speedup_net_vs_coarse_jacobi"] = out["coarse_jacobi"]["seconds_mean"] / out["coarse_net"]["seconds_mean"]
+    lp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +218,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0 = skip)")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-train", type=int, default=40, help="training draws of the learned preconditioner")
+    ap.add_argument("--learned-held", type=int, default=4, help="held-out draws of the learned comparison")
+    ap.add_argument("--learned-weights", default=None, help="load parameters from this file instead of training")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--sweep", action="store_true")
@@ -259,6 +297,9 @@ def main():
     if not args.no_mixed:
         out["mixed"] = run_mixed(hexpa)
         log("mixed-precision comparison done")
+    if not args.no_learned:
+        out["learned"] = run_learned(hexpa, args.learned_train, args.learned_held, weights=args.learned_weights)
+        log("learned-preconditioner comparison done")
     if args.sweep:
         sweep = []
         for pp, nn in ((2, 155), (4, 78), (6, 52), (8, 40)):

@@ -210,11 +210,12 @@ int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
    (3x3x3 cross-correlation, zero padding, bias; 2 -> 16 -> 16 -> 1 channels, ReLU between
    layers) whose input channels are G_e r / s_e (s_e = RMS of G_e r over the tile) and
    log kappa at the nodes, and whose output is multiplied by s_e, so the map is positively
-   1-homogeneous in r.  W = 1 / (number of elements sharing a DOF): element outputs are
-   averaged.  P1 = nodal interpolation from the p = 1 space on the same mesh, A1 = the p = 1
+   1-homogeneous in r (exactly so in FP32 for power-of-two scalings).  W = 1 / (number of
+   elements sharing a DOF): element outputs are averaged.  P1 = nodal interpolation from the p = 1 space on the same mesh, A1 = the p = 1
    operator (same coefficient and operator bits, 3-point Gauss), constrained on the box
    boundary; A1^{-1} is a fixed number of Jacobi-PCG iterations from 0 on A1's 27-point
-   stencil.  Network arithmetic is FP32 (parameters FP32); vectors FP64.
+   stencil.  Parameters are FP32; training runs the network in FP32; inference runs it in
+   FP32 or in FP16 with FP32 accumulation (infer_fp16); vectors are FP64.
    Parameters: flat FP32 array W1 [16][2][27], b1 [16], W2 [16][16][27], b2 [16],
    W3 [1][16][27], b3 [1] with tap = tx + 3 ty + 9 tz for the neighbour
    (i + tx - 1, j + ty - 1, k + tz - 1) of local node (i, j, k). */
@@ -226,7 +227,8 @@ typedef struct {
     int32_t coarse_iters; /* Jacobi-PCG iterations of the coarse solve, >= 1 */
     int32_t loss;         /* PA_LP_LOSS_* */
     int32_t seed;         /* seed of the default (He-normal) parameter initialisation */
-    int32_t pad_;
+    int32_t infer_fp16;   /* 1: apply the network with FP16 MFMA (FP32 accumulation) in one
+                             fused kernel; 0: FP32 vector-ALU kernels (training always uses FP32) */
     double lr;            /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
 } pa_lp_opts;
 

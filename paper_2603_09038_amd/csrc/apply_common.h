@@ -50,6 +50,10 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kLdsBudget = HEXPA_LDS_BUDGET;  // bytes of LDS per workgroup
 constexpr int kMfmaBatch = HEXPA_MFMA_BATCH;  // MFMA tiles in flight per wave
 constexpr int kValuBatch = HEXPA_VALU_BATCH;  // GEMM columns in flight per thread
+#ifndef HEXPA_VALU_SPLIT
+#define HEXPA_VALU_SPLIT 0
+#endif
+constexpr int kValuSplit = HEXPA_VALU_SPLIT;  // max threads sharing one column's outputs (0/1: none)
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -217,27 +221,48 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
 }
 
 // ------------------------------------------------------------------ VALU executor
-// One thread per GEMM column, all O outputs in registers; BATCH columns per thread are
-// loaded before any FMA so the LDS latency of one column hides behind another.
+// Thread per GEMM column and output part: when a pass has fewer columns than threads, the
+// O outputs of a column may be split over up to kValuSplit threads (the part is uniform
+// over a wave; consecutive threads take consecutive columns, so LDS reads stay
+// conflict-free); each thread keeps its outputs in registers.  BATCH work items per
+// thread are loaded before any FMA so the LDS latency of one hides behind another.
+template <class P, int E>
+struct ValuShape {
+    static constexpr int NCOLS = E * P::NCOL;
+    static constexpr int NCOLP = ((NCOLS + 63) / 64) * 64;  // whole waves per output part
+    static constexpr int S = (kValuSplit >= 4 && 4 * NCOLP <= kThreads && P::O >= 8)   ? 4
+                             : (kValuSplit >= 2 && 2 * NCOLP <= kThreads && P::O >= 4) ? 2
+                                                                                        : 1;
+    static constexpr int OP = (P::O + S - 1) / S;  // outputs per thread
+    static constexpr int NTOT = S == 1 ? NCOLS : NCOLP * S;
+};
+
 template <class P, int E, class Out>
 __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevTables *tab, const Out &out, int tid)
 {
     constexpr int C = P::C, NT = P::NT, O = P::O;
-    constexpr int NTOT = E * P::NCOL;
+    using V = ValuShape<P, E>;
+    constexpr int NTOT = V::NTOT, OP = V::OP;
     constexpr int NR = (NTOT + kThreads - 1) / kThreads;
     constexpr int BATCH = NR < kValuBatch ? NR : kValuBatch;
 #pragma unroll 1
     for (int r0 = 0; r0 < NR; r0 += BATCH) {
         double xin[BATCH][NT * C];
-        int eI[BATCH], nI[BATCH];
+        int eI[BATCH], nI[BATCH], o0[BATCH];
         bool cv[BATCH];
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
-            const int col = tid + kThreads * (r0 + bi);
-            cv[bi] = (r0 + bi < NR) && col < NTOT;
-            const int cc = cv[bi] ? col : 0;
-            eI[bi] = cc / P::NCOL;
-            nI[bi] = cc - eI[bi] * P::NCOL;
+            const int it = tid + kThreads * (r0 + bi);
+            int col = it, part = 0;
+            if constexpr (V::S > 1) {
+                part = __builtin_amdgcn_readfirstlane(it / V::NCOLP);
+                col = it - part * V::NCOLP;
+            }
+            cv[bi] = (r0 + bi < NR) && it < NTOT && col < V::NCOLS;
+            if (!cv[bi]) col = 0;
+            o0[bi] = part * OP;
+            eI[bi] = col / P::NCOL;
+            nI[bi] = col - eI[bi] * P::NCOL;
             const double *base = in + eI[bi] * szin + nI[bi] * C;
 #pragma unroll
             for (int t = 0; t < NT; ++t)
@@ -246,16 +271,25 @@ __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevT
         }
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
-            double acc[O];
+            double acc[OP];
 #pragma unroll
-            for (int o = 0; o < O; ++o) acc[o] = 0.0;
+            for (int o = 0; o < OP; ++o) acc[o] = 0.0;
+            if constexpr (V::S == 1) {
 #pragma unroll
-            for (int k = 0; k < NT * C; ++k)
+                for (int k = 0; k < NT * C; ++k)
 #pragma unroll
-                for (int o = 0; o < O; ++o) acc[o] = fma(P::A(tab, o, k), xin[bi][k], acc[o]);
+                    for (int o = 0; o < OP; ++o) acc[o] = fma(P::A(tab, o, k), xin[bi][k], acc[o]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NT * C; ++k)
+#pragma unroll
+                    for (int o = 0; o < OP; ++o)
+                        if (o0[bi] + o < O) acc[o] = fma(P::A(tab, o0[bi] + o, k), xin[bi][k], acc[o]);
+            }
             if (cv[bi]) {
 #pragma unroll
-                for (int o = 0; o < O; ++o) out.put(eI[bi], P::OUT + nI[bi] + P::NCOL * o, acc[o]);
+                for (int o = 0; o < OP; ++o)
+                    if (o0[bi] + o < O) out.put(eI[bi], P::OUT + nI[bi] + P::NCOL * (o0[bi] + o), acc[o]);
             }
         }
     }

@@ -25,7 +25,25 @@
 #define HEXPA_MIN_BLOCKS 3
 #endif
 
+#ifndef HEXPA_LDS_BARRIER
+#define HEXPA_LDS_BARRIER 0
+#endif
+
 namespace hexpa {
+
+// Workgroup barrier for LDS traffic only.  __syncthreads() also orders global memory at
+// workgroup scope, which on gfx950 means s_waitcnt vmcnt(0) before every barrier: every
+// prefetched map/x load and every scatter atomic in flight would be waited for.  The
+// waves of a workgroup exchange data only through LDS, so waiting for LDS (lgkmcnt) is
+// enough; loads whose registers are used later are still waited for by the compiler.
+__device__ __forceinline__ void lds_barrier()
+{
+#if HEXPA_LDS_BARRIER
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+#else
+    __syncthreads();
+#endif
+}
 
 constexpr bool kPrefetchD = HEXPA_PREFETCH_D != 0;  // double-buffer D in registers across groups
 constexpr bool kLateD = HEXPA_LATE_D != 0;          // load D at the D-step (no prefetch)
@@ -175,29 +193,29 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
         load_map<S>(mnext, emap, elist, e0n, nvn, tid);
         T dnext[kPrefetchD ? NS : 1][NC];
         if constexpr (kPrefetchD) load_qdata<S>(dnext, qd, elist, e0n, nvn, tid);
-        __syncthreads();
+        lds_barrier();
 
         // forward contractions
         if constexpr (S::kDiff) {
             run_pass<DF1<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            __syncthreads();
+            lds_barrier();
             run_pass<DF2a<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             run_pass<DF2b<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            __syncthreads();
+            lds_barrier();
             run_pass<DF3a<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             run_pass<DF3b<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             run_pass<DF3c<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
         } else {
             run_pass<MF1<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            __syncthreads();
+            lds_barrier();
             run_pass<MF2<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            __syncthreads();
+            lds_barrier();
             run_pass<MF3<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
         }
         // the next group's map has had the forward passes to arrive: start its x gather
         T xnext[NM];
         load_x<S>(xnext, mnext, x);
-        __syncthreads();
+        lds_barrier();
 
         // D at quadrature points: v = D grad_ref u (symmetric 3x3) and/or v_u = D_m u
         if constexpr (kLateD) load_qdata<S>(dq, qd, elist, e0, nv, tid);
@@ -230,7 +248,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
                 load_qdata<S>(dq, qd, elist, e0n, nvn, tid);
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         // transposed contractions and scatter-add
         if constexpr (S::kDiff) {
@@ -241,20 +259,20 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
             if constexpr (M)
                 run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
                                                                 tid);
-            __syncthreads();
+            lds_barrier();
             run_pass<DT2a<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             run_pass<DT2b<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            __syncthreads();
+            lds_barrier();
             run_pass<DT3<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
         } else {
             run_pass<MT1<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            __syncthreads();
+            lds_barrier();
             run_pass<MT2<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            __syncthreads();
+            lds_barrier();
             run_pass<MT3<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
         }
         if (!more) break;
-        __syncthreads();  // LDS (X, map) is rewritten by the next group
+        lds_barrier();  // LDS (X, map) is rewritten by the next group
         g = gn;
 #pragma unroll
         for (int s = 0; s < NM; ++s) {
@@ -264,15 +282,255 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
     }
 }
 
+// ------------------------------------------------------------------ DMA-staged variant
+// Every global load of the element loop goes straight into LDS (global_load_lds: 16 bytes
+// per lane for D, 4 bytes per lane for the DOF map and for the two halves of each
+// gathered x value), issued from inline assembly so that the compiler neither waits for
+// them nor counts them; the kernel waits for all of them at one point per group, the
+// D-step, where D is needed anyway.  Per group g:
+//   stage x(g) from LDS | issue x(g+1) (map(g+1) already in LDS) and map(g+2) |
+//   forward passes | wait, D-step | issue D(g+1) | transposed passes and scatter.
+// So the D stream of the next group overlaps the transposed passes and the forward
+// passes, and the gathers overlap the forward passes, without holding registers.
+#ifndef HEXPA_APPLY_DMA
+#define HEXPA_APPLY_DMA 0
+#endif
+#ifndef HEXPA_DMA_LDS_BUDGET
+#define HEXPA_DMA_LDS_BUDGET (53 * 1024)
+#endif
+
+__device__ __forceinline__ uint32_t lds_byte_addr(const void *p)
+{
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+// lane l writes [base + size l, base + size (l + 1)) of LDS; base is made wave-uniform.
+// M0 (the LDS base register of these loads) is saved and restored inside the statement.
+__device__ __forceinline__ void dma16(const void *src, uint32_t base)
+{
+    uint32_t saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "v"(src), "s"(__builtin_amdgcn_readfirstlane(base))
+        : "memory");
+}
+__device__ __forceinline__ void dma4(const void *src, uint32_t base)
+{
+    uint32_t saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %1, off\n\ts_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "v"(src), "s"(__builtin_amdgcn_readfirstlane(base))
+        : "memory");
+}
+__device__ __forceinline__ void dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <int D, int Q, int OPS, class T>
+struct DmaShape {
+    using B = Shape<D, Q, OPS, (int)sizeof(T)>;
+    static constexpr int TB = (int)sizeof(T);
+    static constexpr int PER = TB * (B::SZ_A + B::SZ_B) + 12 * B::D3 + (TB == 8 ? 8 : 4) * B::D3 + TB * B::NCOMP * B::Q3;
+    static constexpr int FIXED = TB * 2 * B::SLACK + (int)sizeof(DevTables);
+    static constexpr int E = cclamp((HEXPA_DMA_LDS_BUDGET - FIXED) / PER, 1, 32);
+    static constexpr bool ok = HEXPA_APPLY_DMA != 0 && E >= 2 && (B::NCOMP * B::Q3 * TB) % 16 == 0;
+};
+
+template <int D, int Q, int OPS, int EX, bool ATOMIC>
+__global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
+    int nelem, int ngroups, const int32_t *__restrict__ elist, const int32_t *__restrict__ emap,
+    const typename ExT<EX>::T *__restrict__ qd, const DevTables *__restrict__ tab,
+    const typename ExT<EX>::T *__restrict__ x, typename ExT<EX>::T *__restrict__ y)
+{
+    using T = typename ExT<EX>::T;
+    using S = Shape<D, Q, OPS, (int)sizeof(T)>;
+    constexpr int E = DmaShape<D, Q, OPS, T>::E, D3 = S::D3, Q3 = S::Q3, NC = S::NCOMP, ED3 = E * D3;
+    constexpr int NSD = (E * Q3 + kThreads - 1) / kThreads;
+    constexpr int TPC = 16 / (int)sizeof(T), CPE = NC * Q3 / TPC, ECH = E * CPE;
+    constexpr bool M = S::kMass, WIDE = sizeof(T) == 8;
+    constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
+    __shared__ T sD[E * NC * Q3];
+    __shared__ T bufA[E * S::SZ_A + S::SLACK];
+    __shared__ T bufB[E * S::SZ_B + S::SLACK];
+    __shared__ int32_t mapb[3][ED3];
+    __shared__ uint32_t XL[ED3], XH[WIDE ? ED3 : 1];
+    __shared__ DevTables stab;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += kThreads)
+        reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
+
+    const int nb = gridDim.x;
+    int g, gend, nbx;
+    if (nb >= 8) {
+        const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+        nbx = (nb >> 3) + (xcd < (nb & 7) ? 1 : 0);
+        gend = (int)(((int64_t)ngroups * (xcd + 1)) >> 3);
+        g = (int)(((int64_t)ngroups * xcd) >> 3) + slot;
+    } else {
+        nbx = nb;
+        gend = ngroups;
+        g = blockIdx.x;
+    }
+    if (g >= gend) return;
+
+    // map of group gg into buffer b (absent element slots get -1)
+    auto issue_map = [&](int gg, int b) {
+        const int e0 = gg * E, nv = min(E, nelem - e0);
+        for (int L0 = wave * 64; L0 < ED3; L0 += kThreads) {
+            const int L = L0 + lane;
+            const uint32_t base = lds_byte_addr(&mapb[b][L0]);
+            if (L < nv * D3) {
+                const int e = L / D3, I = L - e * D3;
+                const int64_t ge = EL ? elist[e0 + e] : e0 + e;
+                dma4(emap + ge * D3 + I, base);
+            } else if (L < ED3) {
+                mapb[b][L] = -1;
+            }
+        }
+    };
+    // x gathered through the map in buffer b (absent slots read x[0], never scattered)
+    auto issue_x = [&](int b) {
+        for (int L0 = wave * 64; L0 < ED3; L0 += kThreads) {
+            const int L = L0 + lane;
+            const uint32_t bl = lds_byte_addr(&XL[L0]);
+            const uint32_t bh = WIDE ? lds_byte_addr(&XH[L0]) : 0u;
+            if (L < ED3) {
+                const int m = mapb[b][L];
+                const T *src = x + (m >= 0 ? m : 0);
+                dma4(src, bl);
+                if constexpr (WIDE) dma4(reinterpret_cast<const char *>(src) + 4, bh);
+            }
+        }
+    };
+    auto issue_d = [&](int gg) {
+        const int e0 = gg * E, nv = min(E, nelem - e0), nch = nv * CPE;
+        for (int c0 = wave * 64; c0 < ECH; c0 += kThreads) {
+            const int ch = c0 + lane;
+            const uint32_t base = lds_byte_addr(sD + c0 * TPC);
+            if (ch < nch) {
+                const int e = ch / CPE, w = ch - e * CPE;
+                const int64_t ge = EL ? elist[e0 + e] : e0 + e;
+                dma16(qd + ge * (int64_t)(NC * Q3) + w * TPC, base);
+            }
+        }
+    };
+
+    // prologue: maps of the first two groups, D of the first, then its x
+    issue_map(g, 0);
+    if (g + nbx < gend) issue_map(g + nbx, 1);
+    issue_d(g);
+    dma_wait();
+    lds_barrier();
+    issue_x(0);
+    dma_wait();
+    lds_barrier();
+
+    int mb = 0;  // buffer holding this group's map
+    for (;;) {
+        const int gn = g + nbx, gn2 = gn + nbx;
+        const bool more = gn < gend, more2 = gn2 < gend;
+        const int mb1 = mb == 2 ? 0 : mb + 1, mb2 = mb1 == 2 ? 0 : mb1 + 1;
+
+        // stage x_E from the gathered halves
+        for (int L = tid; L < ED3; L += kThreads) {
+            const int e = L / D3, I = L - e * D3;
+            T v;
+            if constexpr (WIDE) v = __hiloint2double((int)XH[L], (int)XL[L]);
+            else v = __uint_as_float(XL[L]);
+            bufA[e * S::SZ_A + I] = v;
+        }
+        lds_barrier();
+        if (more) issue_x(mb1);
+        if (more2) issue_map(gn2, mb2);
+
+        // forward contractions
+        if constexpr (S::kDiff) {
+            run_pass<DF1<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            lds_barrier();
+            run_pass<DF2a<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DF2b<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            lds_barrier();
+            run_pass<DF3a<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3b<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3c<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+        } else {
+            run_pass<MF1<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            lds_barrier();
+            run_pass<MF2<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            lds_barrier();
+            run_pass<MF3<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+        }
+        // D of this group, the next group's x and the map after it have landed
+        dma_wait();
+        lds_barrier();
+
+#pragma unroll
+        for (int s = 0; s < NSD; ++s) {
+            const int L = tid + s * kThreads;
+            if (L < E * Q3) {
+                const int e = L / Q3, r = L - e * Q3;
+                T *V = bufB + e * S::SZ_B + r;
+                const T *Dm = sD + e * NC * Q3 + r;
+                if constexpr (S::kDiff) {
+                    using CH = Chan<Q, M>;
+                    const T g0 = V[CH::X], g1 = V[CH::Y], g2 = V[CH::Z];
+                    const T d0 = Dm[0], d1 = Dm[Q3], d2 = Dm[2 * Q3], d3 = Dm[3 * Q3], d4 = Dm[4 * Q3], d5 = Dm[5 * Q3];
+                    V[CH::X] = d0 * g0 + d1 * g1 + d2 * g2;
+                    V[CH::Y] = d1 * g0 + d3 * g1 + d4 * g2;
+                    V[CH::Z] = d2 * g0 + d4 * g1 + d5 * g2;
+                    if constexpr (M) V[CH::V] = Dm[6 * Q3] * V[CH::V];
+                } else {
+                    V[0] *= Dm[0];
+                }
+            }
+        }
+        lds_barrier();
+        if (more) issue_d(gn);
+
+        // transposed contractions and scatter-add
+        const int32_t *lmap = mapb[mb];
+        if constexpr (S::kDiff) {
+            using CH = Chan<Q, M>;
+            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            if constexpr (M)
+                run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
+                                                                tid);
+            lds_barrier();
+            run_pass<DT2a<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DT2b<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            lds_barrier();
+            run_pass<DT3<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
+        } else {
+            run_pass<MT1<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            lds_barrier();
+            run_pass<MT2<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            lds_barrier();
+            run_pass<MT3<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
+        }
+        if (!more) break;
+        lds_barrier();  // bufA, XL/XH and the oldest map buffer are rewritten next
+        g = gn;
+        mb = mb1;
+    }
+    // no load is left in flight at exit: the last group issued none after its wait
+}
+
 // ------------------------------------------------------------------ launchers
 template <int D, int Q, int OPS, int EX, bool ATOMIC>
 static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const typename ExT<EX>::T *x,
                            typename ExT<EX>::T *y, const int32_t *elist, int n, hipStream_t s)
 {
-    using S = Shape<D, Q, OPS, (int)sizeof(typename ExT<EX>::T)>;
-    const int ngroups = (n + S::E - 1) / S::E;
+    using T = typename ExT<EX>::T;
+    constexpr bool DMA = DmaShape<D, Q, OPS, T>::ok;
+    constexpr int EG = DMA ? DmaShape<D, Q, OPS, T>::E : Shape<D, Q, OPS, (int)sizeof(T)>::E;
+    const int ngroups = (n + EG - 1) / EG;
     if (ngroups == 0) return hipSuccess;
-    auto kern = k_apply<D, Q, OPS, EX, ATOMIC>;
+    void (*kern)(int, int, const int32_t *, const int32_t *, const T *, const DevTables *, const T *, T *);
+    if constexpr (DMA) kern = k_apply_dma<D, Q, OPS, EX, ATOMIC>;
+    else kern = k_apply<D, Q, OPS, EX, ATOMIC>;
     int nblocks = ngroups;
     if (kOversub > 0) {
         // resident capacity of the device for this kernel (queried once)

@@ -27,6 +27,11 @@ hipError_t nn_forward(int n, int64_t nelem, const float *params, float *wt, cons
 hipError_t nn_backward(int n, int64_t nelem, const float *params, const float *x0, const float *a1, const float *a2,
                        const float *gout, float *ga2, float *ga1, float *grads, float *wt, float *partial,
                        hipStream_t s);
+// Inference in one kernel with FP16 MFMA (FP32 accumulation): z += W G^T (s_e NN(...)).
+// wpack: nn_pack16_bytes() of device scratch for the lane-ordered FP16 weights.
+int64_t nn_pack16_bytes();
+hipError_t nn_infer16(int n, int64_t nelem, const float *params, void *wpack, const double *r, const int32_t *emap,
+                      const float *logk, const double *inv_mult, double *z, hipStream_t s);
 // x0 = [G_e r / s_e, logk_e], s_e = RMS of G_e r (1 where it vanishes).
 hipError_t nn_input(int n, int64_t nelem, const double *r, const int32_t *emap, const float *logk, float *x0,
                     float *s, hipStream_t st);

@@ -493,6 +493,206 @@ __global__ __launch_bounds__(256) void k_cpcg_b(int64_t n1, const double *__rest
     });
 }
 
+// ---------------------------------------------------------------- FP16 MFMA inference
+// The whole network part z += W G^T (s_e NN(G_e r / s_e, log kappa_e)) for one element per
+// wave: gather and RMS-normalise the residual tile, three convolutions as implicit GEMMs
+// on v_mfma_f32_16x16x16f16 (FP16 operands, FP32 accumulation), and the averaged scatter.
+// GEMM rows are tile points (16 per row tile), columns output channels, and one k-step of
+// 16 is one tap's 16 input channels (layer 1: four taps of the two input channels padded
+// to four).  Lane layout (pinned by the 16-bit lane-layout test): A lane l holds
+// A[l%16][4(l/16)+t], B lane l holds B[4(l/16)+t][l%16], result lane l element v is
+// D[4(l/16)+v][l%16].  Activations live in LDS as [padded point][channel] FP16 on the
+// (N+2)^3 grid with a zero halo, so every shifted A-operand read is one 8-byte load.
+// Layer 3 (16 -> 1) is Y[pt][tap] = sum_c a2[pt][c] W3[c][tap] on MFMA followed by
+// out[pt] = b3 + sum_tap Y[pt + off(tap)][tap] over the taps that stay in the tile.
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+constexpr int kPackL1 = 7, kPackL2 = 27, kPackL3 = 2, kPackSteps = kPackL1 + kPackL2 + kPackL3;
+
+// B-operand tables in lane order: step s, lane l -> 4 halves (rows 4(l/16)+t, column l%16).
+__global__ void k_pack16(const float *__restrict__ prm, h4_t *__restrict__ wp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kPackSteps * 64) return;
+    const int s = i / 64, l = i % 64, g = l >> 4, col = l & 15;
+    h4_t w;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float v = 0.f;
+        if (s < kPackL1) {  // rows = (tap 4s+g, channel t): W1[o][t][tap], channels 2, 3 zero
+            const int tap = 4 * s + g;
+            if (t < kNetCin && tap < 27) v = prm[kNetOffW1 + (col * kNetCin + t) * 27 + tap];
+        } else if (s < kPackL1 + kPackL2) {  // rows = channel 4g+t of tap s-7: W2[o][c][tap]
+            const int tap = s - kPackL1, c = 4 * g + t;
+            v = prm[kNetOffW2 + (col * kNetCh + c) * 27 + tap];
+        } else {  // rows = channel 4g+t, columns = taps 16 ct + col: W3[0][c][tap]
+            const int ct = s - kPackL1 - kPackL2, c = 4 * g + t, tap = 16 * ct + col;
+            if (tap < 27) v = prm[kNetOffW3 + c * 27 + tap];
+        }
+        w[t] = (_Float16)v;
+    }
+    wp[i] = w;
+}
+
+template <int N>
+struct Pad {
+    static constexpr int P = N * N * N, NP = N + 2, NP3 = NP * NP * NP, RT = (P + 15) / 16;
+    __host__ __device__ static constexpr int off(int tap)
+    {
+        return (tap % 3 - 1) + NP * ((tap / 3) % 3 - 1) + NP * NP * (tap / 9 - 1);
+    }
+    __device__ static int pad(int pt)
+    {
+        const int i = pt % N, j = (pt / N) % N, k = pt / (N * N);
+        return (i + 1) + NP * ((j + 1) + NP * (k + 1));
+    }
+    __device__ static bool halo(int q)
+    {
+        const int i = q % NP, j = (q / NP) % NP, k = q / (NP * NP);
+        return i == 0 || j == 0 || k == 0 || i == NP - 1 || j == NP - 1 || k == NP - 1;
+    }
+};
+
+template <int N>
+__global__ __launch_bounds__(64) void k_net16(int64_t nelem, const double *__restrict__ r,
+                                              const int32_t *__restrict__ emap, const float *__restrict__ logk,
+                                              const h4_t *__restrict__ wp, const float *__restrict__ prm,
+                                              const double *__restrict__ inv_mult, double *__restrict__ z)
+{
+    using T = Pad<N>;
+    constexpr int P = T::P, NP3 = T::NP3, RT = T::RT, NPL = (P + 63) / 64;
+    static_assert(RT * 16 * 32 <= NP3 * 16, "layer-3 table fits in the a1 buffer");
+    __shared__ h4_t x0b[NP3];      // [point] (r/s, log kappa, 0, 0)
+    __shared__ h4_t a1b[NP3 * 4];  // [point][channel group of 4]
+    __shared__ h4_t a2b[NP3 * 4];
+    _Float16 *a1h = reinterpret_cast<_Float16 *>(a1b), *a2h = reinterpret_cast<_Float16 *>(a2b);
+    _Float16 *yb = a1h;  // layer-3 table [row < 16 RT][32 taps] reuses a1's space
+    const int l = threadIdx.x, g = l >> 4, col = l & 15;
+    const h4_t zero4 = {0, 0, 0, 0};
+    for (int i = l; i < NP3; i += 64) {
+        x0b[i] = zero4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a1b[i * 4 + k] = a2b[i * 4 + k] = zero4;
+    }
+    h4_t w1[kPackL1], w2[kPackL2], w3[kPackL3];
+#pragma unroll
+    for (int s = 0; s < kPackL1; ++s) w1[s] = wp[s * 64 + l];
+#pragma unroll
+    for (int s = 0; s < kPackL2; ++s) w2[s] = wp[(kPackL1 + s) * 64 + l];
+#pragma unroll
+    for (int s = 0; s < kPackL3; ++s) w3[s] = wp[(kPackL1 + kPackL2 + s) * 64 + l];
+    const float bias1 = prm[kNetOffB1 + col], bias2 = prm[kNetOffB2 + col], bias3 = prm[kNetOffB3];
+    int rb[RT];  // padded index of this lane's GEMM row in every row tile (dummy rows repeat the last point)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) rb[rt] = T::pad(min(16 * rt + col, P - 1));
+    // layer-1 tap offset of this lane's k-group in every k-step (taps past 26 carry zero weights)
+    int o1[kPackL1];
+#pragma unroll
+    for (int s = 0; s < kPackL1; ++s) o1[s] = 4 * s + g < 27 ? T::off(4 * s + g) : 0;
+    __syncthreads();
+
+    for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
+        // gather r, element RMS, network input
+        double rv[NPL];
+        int32_t gi[NPL];
+        double ss = 0.0;
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+            const int p = l + 64 * k;
+            rv[k] = 0.0;
+            gi[k] = 0;
+            if (p < P) {
+                gi[k] = emap[e * P + p];
+                rv[k] = r[gi[k]];
+                ss = fma(rv[k], rv[k], ss);
+            }
+        }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m);
+        const double rms = sqrt(ss / P);
+        const double sc = rms > 0.0 ? rms : 1.0;
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+            const int p = l + 64 * k;
+            if (p < P) {
+                h4_t v = {(_Float16)(float)(rv[k] / sc), (_Float16)logk[e * P + p], (_Float16)0.f, (_Float16)0.f};
+                x0b[T::pad(p)] = v;
+            }
+        }
+        __syncthreads();
+
+        f4_t acc[RT];
+        // layer 1: 2 (padded to 4) -> 16 channels, ReLU
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = (f4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < kPackL1; ++s)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16f16(x0b[rb[rt] + o1[s]], w1[s], acc[rt], 0, 0, 0);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int p = 16 * rt + 4 * g + v;
+                if (p < P) a1h[T::pad(p) * 16 + col] = (_Float16)fmaxf(acc[rt][v] + bias1, 0.f);
+            }
+        __syncthreads();
+        // layer 2: 16 -> 16, one tap per k-step, ReLU
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = (f4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 27; ++s)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1b[(rb[rt] + T::off(s)) * 4 + g], w2[s], acc[rt], 0,
+                                                                0, 0);
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int p = 16 * rt + 4 * g + v;
+                if (p < P) a2h[T::pad(p) * 16 + col] = (_Float16)fmaxf(acc[rt][v] + bias2, 0.f);
+            }
+        __syncthreads();
+        // layer 3, part 1: Y[pt][tap] for every tile point and tap
+#pragma unroll
+        for (int ct = 0; ct < kPackL3; ++ct)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const f4_t y = __builtin_amdgcn_mfma_f32_16x16x16f16(a2b[rb[rt] * 4 + g], w3[ct],
+                                                                     (f4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) yb[(16 * rt + 4 * g + v) * 32 + 16 * ct + col] = (_Float16)y[v];
+            }
+        __syncthreads();
+        // layer 3, part 2: shifted sum over taps, then the averaged scatter
+#pragma unroll
+        for (int k = 0; k < NPL; ++k) {
+            const int p = l + 64 * k;
+            if (p < P) {
+                float mk[27];
+                tap_mask<N>(p, mk);
+                float o = bias3;
+#pragma unroll
+                for (int tap = 0; tap < 27; ++tap) {
+                    const int q = p + Tile<N>::off(tap);
+                    const int qc = q < 0 ? 0 : (q >= P ? P - 1 : q);
+                    o = fmaf(mk[tap], (float)yb[qc * 32 + tap], o);
+                }
+                unsafeAtomicAdd(z + gi[k], (double)o * sc * inv_mult[gi[k]]);
+            }
+        }
+        __syncthreads();
+        // the layer-3 table overwrote part of a1's zero halo: restore it
+        for (int i = l; i < RT * 16 * 32 / 16; i += 64)
+            if (T::halo(i))
+#pragma unroll
+                for (int k = 0; k < 4; ++k) a1b[i * 4 + k] = zero4;
+        __syncthreads();
+    }
+}
+
 template <int N>
 hipError_t forward_t(int64_t nelem, const float *params, float *wt, const float *x0, float *a1, float *a2,
                      float *out, hipStream_t s)
@@ -562,6 +762,23 @@ hipError_t nn_forward(int n, int64_t nelem, const float *params, float *wt, cons
     if (n == 4) return forward_t<4>(nelem, params, wt, x0, a1, a2, out, s);
     if (n == 5) return forward_t<5>(nelem, params, wt, x0, a1, a2, out, s);
     return hipErrorInvalidValue;
+}
+
+int64_t nn_pack16_bytes() { return (int64_t)kPackSteps * 64 * sizeof(h4_t); }
+
+hipError_t nn_infer16(int n, int64_t nelem, const float *params, void *wpack, const double *r, const int32_t *emap,
+                      const float *logk, const double *inv_mult, double *z, hipStream_t s)
+{
+    if (nelem <= 0) return hipSuccess;
+    h4_t *wp = static_cast<h4_t *>(wpack);
+    hipLaunchKernelGGL(k_pack16, dim3((kPackSteps * 64 + 255) / 256), dim3(256), 0, s, params, wp);
+    // persistent waves: enough to fill every CU several times over
+    const unsigned nb = (unsigned)std::min<int64_t>(nelem, 256 * 8);
+    if (n == 3) hipLaunchKernelGGL(k_net16<3>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, z);
+    else if (n == 4) hipLaunchKernelGGL(k_net16<4>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, z);
+    else if (n == 5) hipLaunchKernelGGL(k_net16<5>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, z);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t nn_backward(int n, int64_t nelem, const float *params, const float *x0, const float *a1, const float *a2,

@@ -26,6 +26,7 @@ struct pa_lp {
     int step = 0;               // Adam steps taken
     // parameters and optimiser state (device FP32)
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr, *wt = nullptr;
+    void *wpack = nullptr;      // lane-ordered FP16 weights of the MFMA inference kernel
     // operator-dependent arrays
     float *logk = nullptr;      // [nelem][P]
     double *inv_mult = nullptr; // [ndof]
@@ -62,7 +63,7 @@ struct pa_lp {
     {
         free_bound();
         for (void *p : {(void *)params, (void *)grads, (void *)adam_m, (void *)adam_v, (void *)wt, (void *)partial,
-                        (void *)red, (void *)dsc})
+                        (void *)red, (void *)dsc, wpack})
             dfree(p);
     }
 };
@@ -77,6 +78,7 @@ int check_opts(const pa_lp_opts *o)
     if (o->use_coarse && o->coarse_iters < 1) return arg_error("pa_lp: coarse_iters must be >= 1");
     if (o->loss != PA_LP_LOSS_ENERGY && o->loss != PA_LP_LOSS_L2) return arg_error("pa_lp: unknown loss");
     if (!(o->lr >= 0.0)) return arg_error("pa_lp: lr must be >= 0");
+    if (o->infer_fp16 != 0 && o->infer_fp16 != 1) return arg_error("pa_lp: infer_fp16 must be 0 or 1");
     return PA_OK;
 }
 
@@ -235,14 +237,19 @@ int ensure_training(pa_lp *lp)
     return PA_OK;
 }
 
-// z = W G^T (s_e NN(x0_e)), zero on the essential DOFs; keeps activations for backward.
-int net_part(pa_lp *lp, const double *r, double *z, hipStream_t s)
+// z = W G^T (s_e NN(x0_e)), zero on the essential DOFs.  The FP32 path keeps the
+// activations for the backward pass; the FP16 path is the fused inference kernel.
+int net_part(pa_lp *lp, const double *r, double *z, hipStream_t s, bool fp16)
 {
     pa_op *op = lp->op;
-    HIP_OK(nn_input(lp->n, lp->nelem, r, op->d_elem_dofs, lp->logk, lp->x0, lp->s, s));
-    HIP_OK(nn_forward(lp->n, lp->nelem, lp->params, lp->wt, lp->x0, lp->a1, lp->a2, lp->out, s));
     HIP_OK(vec_fill(z, 0.0, lp->ndof, s));
-    HIP_OK(nn_output(lp->n, lp->nelem, lp->out, lp->s, op->d_elem_dofs, lp->inv_mult, z, s));
+    if (fp16) {
+        HIP_OK(nn_infer16(lp->n, lp->nelem, lp->params, lp->wpack, r, op->d_elem_dofs, lp->logk, lp->inv_mult, z, s));
+    } else {
+        HIP_OK(nn_input(lp->n, lp->nelem, r, op->d_elem_dofs, lp->logk, lp->x0, lp->s, s));
+        HIP_OK(nn_forward(lp->n, lp->nelem, lp->params, lp->wt, lp->x0, lp->a1, lp->a2, lp->out, s));
+        HIP_OK(nn_output(lp->n, lp->nelem, lp->out, lp->s, op->d_elem_dofs, lp->inv_mult, z, s));
+    }
     if (op->ness) HIP_OK(vec_zero_list(z, op->d_ess, op->ness, s));
     return PA_OK;
 }
@@ -268,7 +275,7 @@ int loss_grad(pa_lp *lp, const double *r, const double *t, hipStream_t s)
     pa_op *op = lp->op;
     const int64_t nd = lp->ndof;
     double *z = lp->v0, *diff = lp->v1, *gz = lp->v2, *At = lp->v3;
-    rc = net_part(lp, r, z, s);
+    rc = net_part(lp, r, z, s, false);
     if (rc) return rc;
     HIP_OK(vec_sub(diff, z, t, nd, s));  // zero on essential DOFs: z and t both vanish there
     if (lp->o.loss == PA_LP_LOSS_ENERGY) {
@@ -315,6 +322,7 @@ extern "C" int pa_lp_create(pa_op *op, const pa_lp_opts *o, pa_lp **out)
     HIP_OK(dalloc(&lp->wt, kNetW1 + kNetW2 + kNetW3));
     HIP_OK(dalloc(&lp->red, 2 * kRedBlocks));
     HIP_OK(dalloc(&lp->dsc, 4));
+    HIP_OK(hipMalloc(&lp->wpack, (size_t)nn_pack16_bytes()));
     const std::vector<float> p0 = default_params(o->seed);
     HIP_OK(hipMemcpy(lp->params, p0.data(), kNetParams * sizeof(float), hipMemcpyHostToDevice));
     HIP_OK(hipMemset(lp->grads, 0, kNetParams * sizeof(float)));
@@ -379,7 +387,7 @@ extern "C" int pa_lp_logk(pa_lp *lp, float *dev_out)
 int hexpa::lp_precondition(pa_lp *lp, const double *r, double *z, hipStream_t s)
 {
     if (lp->o.use_net) {
-        int rc = net_part(lp, r, z, s);
+        int rc = net_part(lp, r, z, s, lp->o.infer_fp16 != 0);
         if (rc) return rc;
     } else {
         HIP_OK(vec_mul(z, lp->dinv, r, lp->ndof, s));
@@ -416,7 +424,7 @@ extern "C" int pa_lp_net(pa_lp *lp, const double *r, double *z, void *stream)
 {
     PA_TRY
     if (!lp || !r || !z) return arg_error("pa_lp_net: NULL argument");
-    return net_part(lp, r, z, as_stream(stream));
+    return net_part(lp, r, z, as_stream(stream), lp->o.infer_fp16 != 0);
     PA_CATCH
 }
 

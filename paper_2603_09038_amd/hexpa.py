@@ -74,7 +74,7 @@ class CgResult(ctypes.Structure):
 
 class LpOpts(ctypes.Structure):
     _fields_ = [("use_net", ctypes.c_int32), ("use_coarse", ctypes.c_int32), ("coarse_iters", ctypes.c_int32),
-                ("loss", ctypes.c_int32), ("seed", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("loss", ctypes.c_int32), ("seed", ctypes.c_int32), ("infer_fp16", ctypes.c_int32),
                 ("lr", ctypes.c_double)]
 
 
@@ -288,8 +288,10 @@ def cg_solve(h, b, x, rtol=1e-8, max_it=10000, mode=PA_CG_JACOBI, check_every=1,
             "fallback": r.fallback}
 
 
-def _lp_opts(use_net=True, use_coarse=True, coarse_iters=20, loss=PA_LP_LOSS_ENERGY, seed=0, lr=1e-3):
-    return LpOpts(int(bool(use_net)), int(bool(use_coarse)), int(coarse_iters), int(loss), int(seed), 0, float(lr))
+def _lp_opts(use_net=True, use_coarse=True, coarse_iters=20, loss=PA_LP_LOSS_ENERGY, seed=0, lr=1e-3,
+             infer_fp16=True):
+    return LpOpts(int(bool(use_net)), int(bool(use_coarse)), int(coarse_iters), int(loss), int(seed),
+                  int(bool(infer_fp16)), float(lr))
 
 
 def pa_lp_create(h, **opts):
