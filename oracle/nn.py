@@ -8,9 +8,12 @@ loops over the 27 taps.  Tiles are indexed [element][channel][k][j][i] (i fastes
 same local node order as the operator (node I = i + d j + d^2 k).
 
 The preconditioner built on it maps a residual r to
-    z = W G^T ( s_e * net([G_e r / s_e, log kappa_E]) )        (network part)
-with s_e the RMS of r over the nodes of element e and W = 1 / (element multiplicity of
-each DOF), i.e. the element outputs are averaged where elements share DOFs.
+    z = W G^T ( s_e * (net(x+) - net(x-)) / 2 ),   x+- = [+-G_e r / s_e, log kappa_E]
+(network part) with s_e the RMS of r over the nodes of element e and W = 1 / (element
+multiplicity of each DOF), i.e. the element outputs are averaged where elements share
+DOFs.  The odd part in r makes the map odd and positively homogeneous, z(a r) = a z(r)
+for every real a, as a CG-type method needs of its preconditioner; the ReLU network
+with biases alone is not odd.
 """
 import numpy as np
 
@@ -85,18 +88,24 @@ def multiplicity(elem_dofs, ndof):
     return np.bincount(elem_dofs.ravel(), minlength=ndof).astype(np.float64)
 
 
-def net_input(r, logk_tiles, elem_dofs, d, eps=1e-300):
-    """Channels [r_E / s_e, log kappa_E]; s_e = RMS of r over the element's nodes."""
+def net_input(r, logk_tiles, elem_dofs, d):
+    """Channels [+-r_E / s_e, log kappa_E] for both signs, stacked as [2E][2][d][d][d]
+    (the first E tiles with +r); s_e = RMS of r over the element's nodes (1 if zero)."""
     rt = element_tiles(r, elem_dofs, d)
-    s = np.sqrt((rt ** 2).reshape(rt.shape[0], -1).mean(axis=1)) + eps
-    x0 = np.stack([rt / s[:, None, None, None], logk_tiles.reshape(-1, d, d, d)], axis=1)
-    return x0, s
+    s = np.sqrt((rt ** 2).reshape(rt.shape[0], -1).mean(axis=1))
+    s = np.where(s > 0.0, s, 1.0)
+    lk = logk_tiles.reshape(-1, d, d, d)
+    xp = np.stack([rt / s[:, None, None, None], lk], axis=1)
+    xm = np.stack([-rt / s[:, None, None, None], lk], axis=1)
+    return np.concatenate([xp, xm], axis=0), s
 
 
 def precond_nn(net, r, logk_tiles, elem_dofs, d, ndof, ess=None):
-    """Network part of the preconditioner: z = W G^T (s_e out_e)."""
+    """Network part of the preconditioner: z = W G^T (s_e (out(x+) - out(x-)) / 2)."""
     x0, s = net_input(r, logk_tiles, elem_dofs, d)
-    out = net.forward(x0)[:, 0] * s[:, None, None, None]
+    o = net.forward(x0)[:, 0]
+    E = s.size
+    out = 0.5 * (o[:E] - o[E:]) * s[:, None, None, None]
     z = np.zeros(ndof)
     np.add.at(z, elem_dofs.ravel(), out.reshape(-1))
     z /= multiplicity(elem_dofs, ndof)
@@ -125,6 +134,7 @@ def loss_and_grads(net, r, t, logk_tiles, elem_dofs, d, ndof, ess, Amul=None):
     gz = np.where(free, 2.0 * Ad / den, 0.0)          # dL/dz
     gz = gz / multiplicity(elem_dofs, ndof)           # through the averaging W
     gout = element_tiles(gz, elem_dofs, d) * s[:, None, None, None]  # through s_e * out
+    gout = 0.5 * np.concatenate([gout, -gout], axis=0)                # through the odd part
     grads, _ = net.backward(gout[:, None])
     return L, grads
 

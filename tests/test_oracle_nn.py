@@ -76,7 +76,7 @@ def test_network_gradients_against_central_differences():
             assert abs(fd - g) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (pi, idx, fd, g)
 
 
-def test_preconditioner_is_one_homogeneous_and_averages():
+def test_preconditioner_is_odd_homogeneous_and_averages():
     mesh, d, ed, ndof, ess, logk, r, t = _setup()
     net = nn.Net(synth.net_params(2, 4, seed=2))
     z1, _ = nn.precond_nn(net, r, logk, ed, d, ndof, ess)
@@ -86,9 +86,19 @@ def test_preconditioner_is_one_homogeneous_and_averages():
     ps = [np.zeros_like(q) for q in net.params()]
     ps[5] = np.ones(1)
     z, (x0, s) = nn.precond_nn(nn.Net(ps), r, logk, ed, d, ndof, None)
-    ref = np.zeros(ndof)
-    np.add.at(ref, ed.ravel(), np.repeat(s, d ** 3))
-    np.testing.assert_allclose(z, ref / nn.multiplicity(ed, ndof), rtol=1e-12)
+    assert np.all(z == 0.0)  # a constant output has no odd part
+    # a network whose output is relu(first input channel) (identity centre taps): the odd
+    # part (relu(x) - relu(-x)) / 2 = x / 2 of x = r_E / s_e, so z = W G^T r_E / 2 = r / 2
+    ps = [np.zeros_like(q) for q in net.params()]
+    ps[0][0, 0, 1, 1, 1] = 1.0   # a1[0] = relu(+-r/s)
+    ps[2][0, 0, 1, 1, 1] = 1.0   # a2[0] = a1[0]
+    ps[4][0, 0, 1, 1, 1] = 1.0   # out = a2[0]
+    z, _ = nn.precond_nn(nn.Net(ps), r, logk, ed, d, ndof, None)
+    np.testing.assert_allclose(z, 0.5 * r, rtol=1e-12, atol=1e-14)
+    # oddness and homogeneity for negative scalings too
+    z1, _ = nn.precond_nn(net, r, logk, ed, d, ndof, ess)
+    z3, _ = nn.precond_nn(net, -2.5 * r, logk, ed, d, ndof, ess)
+    np.testing.assert_allclose(z3, -2.5 * z1, rtol=1e-12, atol=1e-14)
 
 
 def test_adam_minimises_a_quadratic():
