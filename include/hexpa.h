@@ -177,11 +177,11 @@ typedef struct {
     int32_t inner_max;   /* MIXED_IR: inner iterations per refinement step */
     double inner_rtol;   /* MIXED_IR: inner relative tolerance per refinement step */
     pa_lp *lp;           /* FCG: the preconditioner, bound to this operator */
-    int32_t n_capture;   /* JACOBI: number of iterates to record (0: none) */
+    int32_t n_capture;   /* JACOBI, FCG: number of iterates to record (0: none) */
     int32_t pad_;
-    const int32_t *capture_at; /* JACOBI: host [n_capture] ascending iteration numbers k >= 0 */
-    double *capture_x;         /* JACOBI: device [n_capture][ndof]; receives x_k when iteration k
-                                  ends (k = 0: the initial guess); rows of iterations not reached
+    const int32_t *capture_at; /* host [n_capture] ascending iteration numbers k >= 0 */
+    double *capture_x;         /* device [n_capture][ndof]; receives x_k when iteration k ends
+                                  (k = 0: the initial guess); rows of iterations not reached
                                   are left untouched */
 } pa_cg_opts;
 
@@ -205,7 +205,10 @@ int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
 
 /* ------------------------------------------------------------------ learned preconditioner
    Two-level preconditioner for FCG on a structured box with diffusion (p + 1 in {3, 4, 5}):
-       z = W G^T NN(G r) + P1 A1^{-1} P1^T r,        then z = 0 on the essential DOFs.
+       z = J r + W G^T NN(G r) + P1 A1^{-1} P1^T r,   then z = 0 on the essential DOFs,
+   with J = diag(A_c)^{-1} (Jacobi): the network learns a correction to Jacobi, so an
+   untrained network (zero output layer, the default initialisation) gives Jacobi plus
+   the coarse correction.
    NN: per element, a 3-layer convolutional network on the (p+1)^3 nodal tile
    (3x3x3 cross-correlation, zero padding, bias; 2 -> 16 -> 16 -> 1 channels, ReLU between
    layers) whose input channels are G_e r / s_e (s_e = RMS of G_e r over the tile) and
@@ -222,7 +225,7 @@ int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *opts,
 #define PA_LP_LOSS_ENERGY 0 /* L = (z - t)^T A_c (z - t) / t^T A_c t */
 #define PA_LP_LOSS_L2 1     /* L = ||z - t||^2 / ||t||^2 (free DOFs) */
 typedef struct {
-    int32_t use_net;      /* 1: network part; 0: Jacobi diag(A_c)^{-1} r in its place */
+    int32_t use_net;      /* 1: add the network's correction to Jacobi; 0: Jacobi only */
     int32_t use_coarse;   /* 1: add the p = 1 coarse correction */
     int32_t coarse_iters; /* Jacobi-PCG iterations of the coarse solve, >= 1 */
     int32_t loss;         /* PA_LP_LOSS_* */
@@ -230,6 +233,9 @@ typedef struct {
     int32_t infer_fp16;   /* 1: apply the network with FP16 MFMA (FP32 accumulation) in one
                              fused kernel; 0: FP32 vector-ALU kernels (training always uses FP32) */
     double lr;            /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+    double net_scale;     /* factor on the network's correction when the preconditioner is
+                             applied (a damping, like omega of damped Jacobi); training
+                             always uses 1.  Values <= 0 mean 1. */
 } pa_lp_opts;
 
 /* Create a preconditioner bound to op (which must outlive the binding): builds the coarse
@@ -254,15 +260,16 @@ int pa_lp_logk(pa_lp *lp, float *dev_out);
 int pa_lp_apply(pa_lp *lp, const double *r, double *z, void *stream);
 /* z = P1 A1^{-1} P1^T r only (zero on the essential DOFs).  Asynchronous. */
 int pa_lp_coarse(pa_lp *lp, const double *r, double *z, void *stream);
-/* z = W G^T NN(G r) only (zero on the essential DOFs).  Asynchronous. */
+/* z = W G^T NN(G r) only, the network's correction (zero on the essential DOFs).
+   Asynchronous. */
 int pa_lp_net(pa_lp *lp, const double *r, double *z, void *stream);
 /* Loss of the network part z_NN(r) against target t (device, zero on essential DOFs)
    and its gradient w.r.t. the parameters, written to grad_host [n] if not NULL (the
    handle's gradient buffer is overwritten).  Synchronous; *loss receives L. */
 int pa_lp_loss_grad(pa_lp *lp, const double *r, const double *t, double *loss, float *grad_host, void *stream);
 /* One training step on the pair from iterate xk of A_c x = b with known solution xstar:
-   r = b - A_c xk, e = xstar - xk, target t = e - (coarse part of M)(r) when the coarse
-   correction is on (else e); then loss, gradient and one Adam update.  If loss is not
+   r = b - A_c xk, e = xstar - xk, target t = e - J r - (coarse part of M)(r) (the last
+   term when the coarse correction is on); then loss, gradient and one Adam update.  If loss is not
    NULL the call synchronises and stores L.  Asynchronous otherwise. */
 int pa_lp_train_step(pa_lp *lp, const double *b, const double *xstar, const double *xk, double *loss,
                      void *stream);

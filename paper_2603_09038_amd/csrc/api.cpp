@@ -670,11 +670,22 @@ static int solve_fcg(pa_op *op, const double *b, double *x, const pa_cg_opts *o,
     rc = lp_precondition(lp, w.r, z, s);
     if (rc) return rc;
     HIP_OK(fcg_direction(z, w.r, nullptr, w.p, n, w.partial, w.sc, s));
+    // iterates requested by the caller (training-data capture)
+    int cap = 0;
+    auto capture = [&](int k) -> int {
+        if (cap < o->n_capture && o->capture_at[cap] == k) {
+            HIP_OK(vec_copy(o->capture_x + (size_t)cap * n, x, n, s));
+            ++cap;
+        }
+        return PA_OK;
+    };
+    if ((rc = capture(0))) return rc;
     auto step = [&](int it) -> int {
         int r2 = cg_apply(op, con, w.p, w.Ap, s);
         if (r2) return r2;
         HIP_OK(cg_alpha<double>(w.p, w.Ap, n, w.partial, w.sc, s));
         HIP_OK(fcg_update(x, w.r, rold, w.p, w.Ap, n, w.partial, w.sc, w.hist, it, s));
+        if ((r2 = capture(it))) return r2;
         r2 = lp_precondition(lp, w.r, z, s);
         if (r2) return r2;
         HIP_OK(fcg_direction(z, w.r, rold, w.p, n, w.partial, w.sc, s));
@@ -720,8 +731,9 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     if (!(o->rtol > 0.0) || o->max_it < 1) return arg_error("cg_solve: need rtol > 0 and max_it >= 1");
     if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI && o->mode != PA_CG_MIXED_IR && o->mode != PA_CG_FCG)
         return arg_error("cg_solve: unknown mode");
-    if (o->n_capture < 0 || (o->n_capture > 0 && (o->mode != PA_CG_JACOBI || !o->capture_at || !o->capture_x)))
-        return arg_error("cg_solve: capture needs PA_CG_JACOBI, capture_at and capture_x");
+    if (o->n_capture < 0 ||
+        (o->n_capture > 0 && ((o->mode != PA_CG_JACOBI && o->mode != PA_CG_FCG) || !o->capture_at || !o->capture_x)))
+        return arg_error("cg_solve: capture needs PA_CG_JACOBI or PA_CG_FCG, capture_at and capture_x");
     for (int j = 0; j < o->n_capture; ++j)
         if (o->capture_at[j] < 0 || (j > 0 && o->capture_at[j] <= o->capture_at[j - 1]))
             return arg_error("cg_solve: capture_at must be ascending and >= 0");

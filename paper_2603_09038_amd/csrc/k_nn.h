@@ -31,14 +31,15 @@ hipError_t nn_backward(int n, int64_t nelem, const float *params, const float *x
 // wpack: nn_pack16_bytes() of device scratch for the lane-ordered FP16 weights.
 int64_t nn_pack16_bytes();
 hipError_t nn_infer16(int n, int64_t nelem, const float *params, void *wpack, const double *r, const int32_t *emap,
-                      const float *logk, const double *inv_mult, double *z, hipStream_t s);
-// x0 = [G_e r / s_e, logk_e], s_e = RMS of G_e r (1 where it vanishes).
+                      const float *logk, const double *inv_mult, double scale, double *z, hipStream_t s);
+// x0 tiles [2 nelem][2][n^3]: tile e = [G_e r / s_e, logk_e], tile nelem + e = [-G_e r / s_e,
+// logk_e]; s_e = RMS of G_e r (1 where it vanishes).
 hipError_t nn_input(int n, int64_t nelem, const double *r, const int32_t *emap, const float *logk, float *x0,
                     float *s, hipStream_t st);
-// z[g] += s_e out_e[g] inv_mult[g] over all element nodes (z must be zeroed first).
+// z[g] += scale s_e (out_e - out_{nelem+e}) / 2 inv_mult[g] over all element nodes (the odd part).
 hipError_t nn_output(int n, int64_t nelem, const float *out, const float *s, const int32_t *emap,
-                     const double *inv_mult, double *z, hipStream_t st);
-// gout_e = s_e inv_mult[g] gz[g] (adjoint of nn_output).
+                     const double *inv_mult, double scale, double *z, hipStream_t st);
+// gout_e = s_e inv_mult[g] gz[g] / 2, gout_{nelem+e} = -gout_e (adjoint of nn_output).
 hipError_t nn_output_grad(int n, int64_t nelem, const double *gz, const float *s, const int32_t *emap,
                           const double *inv_mult, float *gout, hipStream_t st);
 // inv_mult[g] = 1 / (number of elements holding g).

@@ -202,22 +202,29 @@ __global__ __launch_bounds__(128) void k_nn_input(int64_t nelem, const double *_
     const double rms = sqrt(red[0] / P);
     const double s = rms > 0.0 ? rms : 1.0;
     if (t < P) {
-        x0[(e * 2 + 0) * P + t] = (float)(v / s);
-        x0[(e * 2 + 1) * P + t] = logk[e * P + t];
+        const float xv = (float)(v / s), lk = logk[e * P + t];
+        x0[(e * 2 + 0) * P + t] = xv;  // tile e: +r
+        x0[(e * 2 + 1) * P + t] = lk;
+        x0[((nelem + e) * 2 + 0) * P + t] = -xv;  // tile nelem + e: -r
+        x0[((nelem + e) * 2 + 1) * P + t] = lk;
     }
     if (t == 0) s_out[e] = (float)s;
 }
 
+// z[g] += s_e (out(+r)_e - out(-r)_e) / 2 * inv_mult[g]: the odd part of the network,
+// averaged over the elements sharing g.  out holds the +r tiles, then the -r tiles.
 __global__ void k_nn_output(int64_t total, int P, const float *__restrict__ out, const float *__restrict__ s,
-                            const int32_t *__restrict__ emap, const double *__restrict__ inv_mult,
+                            const int32_t *__restrict__ emap, const double *__restrict__ inv_mult, double scale,
                             double *__restrict__ z)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int g = emap[idx];
-    unsafeAtomicAdd(z + g, (double)out[idx] * (double)s[idx / P] * inv_mult[g]);
+    const double odd = 0.5 * scale * ((double)out[idx] - (double)out[total + idx]);
+    unsafeAtomicAdd(z + g, odd * (double)s[idx / P] * inv_mult[g]);
 }
 
+// adjoint: d/d out(+r) = s_e gz inv_mult / 2, d/d out(-r) = its negative
 __global__ void k_nn_output_grad(int64_t total, int P, const double *__restrict__ gz, const float *__restrict__ s,
                                  const int32_t *__restrict__ emap, const double *__restrict__ inv_mult,
                                  float *__restrict__ gout)
@@ -225,7 +232,9 @@ __global__ void k_nn_output_grad(int64_t total, int P, const double *__restrict_
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
     const int g = emap[idx];
-    gout[idx] = (float)(gz[g] * inv_mult[g] * (double)s[idx / P]);
+    const float v = (float)(0.5 * gz[g] * inv_mult[g] * (double)s[idx / P]);
+    gout[idx] = v;
+    gout[total + idx] = -v;
 }
 
 __global__ void k_count(int64_t total, const int32_t *__restrict__ emap, double *__restrict__ cnt)
@@ -557,7 +566,8 @@ template <int N>
 __global__ __launch_bounds__(64) void k_net16(int64_t nelem, const double *__restrict__ r,
                                               const int32_t *__restrict__ emap, const float *__restrict__ logk,
                                               const h4_t *__restrict__ wp, const float *__restrict__ prm,
-                                              const double *__restrict__ inv_mult, double *__restrict__ z)
+                                              const double *__restrict__ inv_mult, double scale,
+                                              double *__restrict__ z)
 {
     using T = Pad<N>;
     constexpr int P = T::P, NP3 = T::NP3, RT = T::RT, NPL = (P + 63) / 64;
@@ -592,7 +602,7 @@ __global__ __launch_bounds__(64) void k_net16(int64_t nelem, const double *__res
     __syncthreads();
 
     for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
-        // gather r, element RMS, network input
+        // gather r, element RMS
         double rv[NPL];
         int32_t gi[NPL];
         double ss = 0.0;
@@ -611,85 +621,101 @@ __global__ __launch_bounds__(64) void k_net16(int64_t nelem, const double *__res
         for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m);
         const double rms = sqrt(ss / P);
         const double sc = rms > 0.0 ? rms : 1.0;
+        float lk[NPL];
 #pragma unroll
-        for (int k = 0; k < NPL; ++k) {
-            const int p = l + 64 * k;
-            if (p < P) {
-                h4_t v = {(_Float16)(float)(rv[k] / sc), (_Float16)logk[e * P + p], (_Float16)0.f, (_Float16)0.f};
-                x0b[T::pad(p)] = v;
-            }
-        }
-        __syncthreads();
+        for (int k = 0; k < NPL; ++k) lk[k] = (l + 64 * k < P) ? logk[e * P + l + 64 * k] : 0.f;
 
-        f4_t acc[RT];
-        // layer 1: 2 (padded to 4) -> 16 channels, ReLU
+        // the network on +r and on -r; the preconditioner takes the odd part
+        float odd[NPL];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = (f4_t){0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < NPL; ++k) odd[k] = 0.f;
+#pragma unroll 1
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            const double sg = sgn ? -1.0 : 1.0;
 #pragma unroll
-        for (int s = 0; s < kPackL1; ++s)
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16f16(x0b[rb[rt] + o1[s]], w1[s], acc[rt], 0, 0, 0);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int p = 16 * rt + 4 * g + v;
-                if (p < P) a1h[T::pad(p) * 16 + col] = (_Float16)fmaxf(acc[rt][v] + bias1, 0.f);
-            }
-        __syncthreads();
-        // layer 2: 16 -> 16, one tap per k-step, ReLU
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = (f4_t){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 27; ++s)
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1b[(rb[rt] + T::off(s)) * 4 + g], w2[s], acc[rt], 0,
-                                                                0, 0);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int p = 16 * rt + 4 * g + v;
-                if (p < P) a2h[T::pad(p) * 16 + col] = (_Float16)fmaxf(acc[rt][v] + bias2, 0.f);
-            }
-        __syncthreads();
-        // layer 3, part 1: Y[pt][tap] for every tile point and tap
-#pragma unroll
-        for (int ct = 0; ct < kPackL3; ++ct)
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const f4_t y = __builtin_amdgcn_mfma_f32_16x16x16f16(a2b[rb[rt] * 4 + g], w3[ct],
-                                                                     (f4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) yb[(16 * rt + 4 * g + v) * 32 + 16 * ct + col] = (_Float16)y[v];
-            }
-        __syncthreads();
-        // layer 3, part 2: shifted sum over taps, then the averaged scatter
-#pragma unroll
-        for (int k = 0; k < NPL; ++k) {
-            const int p = l + 64 * k;
-            if (p < P) {
-                float mk[27];
-                tap_mask<N>(p, mk);
-                float o = bias3;
-#pragma unroll
-                for (int tap = 0; tap < 27; ++tap) {
-                    const int q = p + Tile<N>::off(tap);
-                    const int qc = q < 0 ? 0 : (q >= P ? P - 1 : q);
-                    o = fmaf(mk[tap], (float)yb[qc * 32 + tap], o);
+            for (int k = 0; k < NPL; ++k) {
+                const int p = l + 64 * k;
+                if (p < P) {
+                    h4_t v = {(_Float16)(float)(sg * rv[k] / sc), (_Float16)lk[k], (_Float16)0.f, (_Float16)0.f};
+                    x0b[T::pad(p)] = v;
                 }
-                unsafeAtomicAdd(z + gi[k], (double)o * sc * inv_mult[gi[k]]);
             }
-        }
-        __syncthreads();
-        // the layer-3 table overwrote part of a1's zero halo: restore it
-        for (int i = l; i < RT * 16 * 32 / 16; i += 64)
-            if (T::halo(i))
+            __syncthreads();
+
+            f4_t acc[RT];
+            // layer 1: 2 (padded to 4) -> 16 channels, ReLU
 #pragma unroll
-                for (int k = 0; k < 4; ++k) a1b[i * 4 + k] = zero4;
-        __syncthreads();
+            for (int rt = 0; rt < RT; ++rt) acc[rt] = (f4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < kPackL1; ++s)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16f16(x0b[rb[rt] + o1[s]], w1[s], acc[rt], 0, 0, 0);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int p = 16 * rt + 4 * g + v;
+                    if (p < P) a1h[T::pad(p) * 16 + col] = (_Float16)fmaxf(acc[rt][v] + bias1, 0.f);
+                }
+            __syncthreads();
+            // layer 2: 16 -> 16, one tap per k-step, ReLU
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc[rt] = (f4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 27; ++s)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1b[(rb[rt] + T::off(s)) * 4 + g], w2[s], acc[rt],
+                                                                    0, 0, 0);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int p = 16 * rt + 4 * g + v;
+                    if (p < P) a2h[T::pad(p) * 16 + col] = (_Float16)fmaxf(acc[rt][v] + bias2, 0.f);
+                }
+            __syncthreads();
+            // layer 3, part 1: Y[pt][tap] for every tile point and tap
+#pragma unroll
+            for (int ct = 0; ct < kPackL3; ++ct)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const f4_t y = __builtin_amdgcn_mfma_f32_16x16x16f16(a2b[rb[rt] * 4 + g], w3[ct],
+                                                                         (f4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) yb[(16 * rt + 4 * g + v) * 32 + 16 * ct + col] = (_Float16)y[v];
+                }
+            __syncthreads();
+            // layer 3, part 2: shifted sum over taps (the bias cancels in the odd part)
+#pragma unroll
+            for (int k = 0; k < NPL; ++k) {
+                const int p = l + 64 * k;
+                if (p < P) {
+                    float mk[27];
+                    tap_mask<N>(p, mk);
+                    float o = bias3;
+#pragma unroll
+                    for (int tap = 0; tap < 27; ++tap) {
+                        const int q = p + Tile<N>::off(tap);
+                        const int qc = q < 0 ? 0 : (q >= P ? P - 1 : q);
+                        o = fmaf(mk[tap], (float)yb[qc * 32 + tap], o);
+                    }
+                    odd[k] += sgn ? -0.5f * o : 0.5f * o;
+                }
+            }
+            __syncthreads();
+            // the layer-3 table overwrote part of a1's zero halo: restore it
+            for (int i = l; i < RT * 16 * 32 / 16; i += 64)
+                if (T::halo(i))
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) a1b[i * 4 + k] = zero4;
+            __syncthreads();
+        }
+        // averaged scatter
+#pragma unroll
+        for (int k = 0; k < NPL; ++k)
+            if (l + 64 * k < P) unsafeAtomicAdd(z + gi[k], (double)odd[k] * sc * scale * inv_mult[gi[k]]);
     }
 }
 
@@ -767,16 +793,16 @@ hipError_t nn_forward(int n, int64_t nelem, const float *params, float *wt, cons
 int64_t nn_pack16_bytes() { return (int64_t)kPackSteps * 64 * sizeof(h4_t); }
 
 hipError_t nn_infer16(int n, int64_t nelem, const float *params, void *wpack, const double *r, const int32_t *emap,
-                      const float *logk, const double *inv_mult, double *z, hipStream_t s)
+                      const float *logk, const double *inv_mult, double scale, double *z, hipStream_t s)
 {
     if (nelem <= 0) return hipSuccess;
     h4_t *wp = static_cast<h4_t *>(wpack);
     hipLaunchKernelGGL(k_pack16, dim3((kPackSteps * 64 + 255) / 256), dim3(256), 0, s, params, wp);
     // persistent waves: enough to fill every CU several times over
     const unsigned nb = (unsigned)std::min<int64_t>(nelem, 256 * 8);
-    if (n == 3) hipLaunchKernelGGL(k_net16<3>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, z);
-    else if (n == 4) hipLaunchKernelGGL(k_net16<4>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, z);
-    else if (n == 5) hipLaunchKernelGGL(k_net16<5>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, z);
+    if (n == 3) hipLaunchKernelGGL(k_net16<3>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
+    else if (n == 4) hipLaunchKernelGGL(k_net16<4>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
+    else if (n == 5) hipLaunchKernelGGL(k_net16<5>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -804,12 +830,12 @@ hipError_t nn_input(int n, int64_t nelem, const double *r, const int32_t *emap, 
 }
 
 hipError_t nn_output(int n, int64_t nelem, const float *out, const float *s, const int32_t *emap,
-                     const double *inv_mult, double *z, hipStream_t st)
+                     const double *inv_mult, double scale, double *z, hipStream_t st)
 {
     const int P = n * n * n;
     const int64_t tot = nelem * P;
     if (tot <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_nn_output, dim3(nblk(tot)), dim3(256), 0, st, tot, P, out, s, emap, inv_mult, z);
+    hipLaunchKernelGGL(k_nn_output, dim3(nblk(tot)), dim3(256), 0, st, tot, P, out, s, emap, inv_mult, scale, z);
     return hipGetLastError();
 }
 

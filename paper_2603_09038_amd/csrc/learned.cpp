@@ -30,7 +30,7 @@ struct pa_lp {
     // operator-dependent arrays
     float *logk = nullptr;      // [nelem][P]
     double *inv_mult = nullptr; // [ndof]
-    double *dinv = nullptr;     // [ndof] 1 / diag(A_c) (network-off variant)
+    double *dinv = nullptr;     // [ndof] 1 / diag(A_c): the Jacobi term of the preconditioner
     // network activations and gradients
     float *x0 = nullptr, *s = nullptr, *a1 = nullptr, *a2 = nullptr, *out = nullptr;
     float *ga1 = nullptr, *ga2 = nullptr, *gout = nullptr, *partial = nullptr;
@@ -40,12 +40,27 @@ struct pa_lp {
     int32_t *cess = nullptr;
     int ncess = 0;
     CoarseScalars *csc = nullptr;
+    // the fixed-iteration coarse solve as one HIP graph (kernel nodes only), rebuilt when
+    // the binding or the iteration count changes
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t cgraph = nullptr;
+    hipGraphExec_t cexec = nullptr;
+    int cgraph_iters = -1;
     // FP64 work vectors [ndof]
     double *v0 = nullptr, *v1 = nullptr, *v2 = nullptr, *v3 = nullptr, *red = nullptr, *dsc = nullptr;
     double *tr_r = nullptr, *tr_t = nullptr;  // training pair (allocated on first use)
 
+    void free_graph()
+    {
+        if (cexec) (void)hipGraphExecDestroy(cexec);
+        if (cgraph) (void)hipGraphDestroy(cgraph);
+        cexec = nullptr;
+        cgraph = nullptr;
+        cgraph_iters = -1;
+    }
     void free_bound()
     {
+        free_graph();
         for (void *p : {(void *)logk, (void *)inv_mult, (void *)dinv, (void *)x0, (void *)s, (void *)a1, (void *)a2,
                         (void *)out, (void *)ga1, (void *)ga2, (void *)gout, (void *)gll, (void *)S, (void *)cdinv,
                         (void *)cr, (void *)cu, (void *)cz, (void *)cp0, (void *)cp1, (void *)cAp, (void *)cpart,
@@ -62,6 +77,7 @@ struct pa_lp {
     ~pa_lp()
     {
         free_bound();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void *p : {(void *)params, (void *)grads, (void *)adam_m, (void *)adam_v, (void *)wt, (void *)partial,
                         (void *)red, (void *)dsc, wpack})
             dfree(p);
@@ -82,7 +98,8 @@ int check_opts(const pa_lp_opts *o)
     return PA_OK;
 }
 
-// He-normal initialisation (std::mt19937_64, Box-Muller by the standard library), biases 0.
+// He-normal initialisation of the hidden layers (std::mt19937_64 and the standard
+// library's normal distribution), zero biases and a zero output layer.
 std::vector<float> default_params(int seed)
 {
     std::vector<float> p(kNetParams, 0.0f);
@@ -94,7 +111,7 @@ std::vector<float> default_params(int seed)
     };
     fill(kNetOffW1, kNetW1, 27.0 * kNetCin, 2.0);
     fill(kNetOffW2, kNetW2, 27.0 * kNetCh, 2.0);
-    fill(kNetOffW3, kNetW3, 27.0 * kNetCh, 1.0);
+    // the output layer starts at zero: the untrained network adds nothing to Jacobi
     return p;
 }
 
@@ -129,11 +146,12 @@ int bind(pa_lp *lp, pa_op *op, hipStream_t s)
     HIP_OK(dalloc(&lp->logk, ne * P));
     HIP_OK(dalloc(&lp->inv_mult, nd));
     HIP_OK(dalloc(&lp->dinv, nd));
-    HIP_OK(dalloc(&lp->x0, ne * kNetCin * P));
+    // network tiles: the +r tile of every element, then the -r tile
+    HIP_OK(dalloc(&lp->x0, 2 * ne * kNetCin * P));
     HIP_OK(dalloc(&lp->s, ne));
-    HIP_OK(dalloc(&lp->a1, ne * kNetCh * P));
-    HIP_OK(dalloc(&lp->a2, ne * kNetCh * P));
-    HIP_OK(dalloc(&lp->out, ne * P));
+    HIP_OK(dalloc(&lp->a1, 2 * ne * kNetCh * P));
+    HIP_OK(dalloc(&lp->a2, 2 * ne * kNetCh * P));
+    HIP_OK(dalloc(&lp->out, 2 * ne * P));
     HIP_OK(dalloc(&lp->v0, nd));
     HIP_OK(dalloc(&lp->v1, nd));
     HIP_OK(dalloc(&lp->v2, nd));
@@ -228,29 +246,49 @@ int bind(pa_lp *lp, pa_op *op, hipStream_t s)
 int ensure_training(pa_lp *lp)
 {
     const int64_t P = (int64_t)lp->n * lp->n * lp->n;
-    if (!lp->ga1) HIP_OK(dalloc(&lp->ga1, lp->nelem * kNetCh * P));
-    if (!lp->ga2) HIP_OK(dalloc(&lp->ga2, lp->nelem * kNetCh * P));
-    if (!lp->gout) HIP_OK(dalloc(&lp->gout, lp->nelem * P));
+    if (!lp->ga1) HIP_OK(dalloc(&lp->ga1, 2 * lp->nelem * kNetCh * P));
+    if (!lp->ga2) HIP_OK(dalloc(&lp->ga2, 2 * lp->nelem * kNetCh * P));
+    if (!lp->gout) HIP_OK(dalloc(&lp->gout, 2 * lp->nelem * P));
     if (!lp->partial) HIP_OK(dalloc(&lp->partial, (size_t)nn_partial_floats()));
     if (!lp->tr_r) HIP_OK(dalloc(&lp->tr_r, lp->ndof));
     if (!lp->tr_t) HIP_OK(dalloc(&lp->tr_t, lp->ndof));
     return PA_OK;
 }
 
-// z = W G^T (s_e NN(x0_e)), zero on the essential DOFs.  The FP32 path keeps the
+// z (+)= W G^T (s_e NN(x0_e)), then zero on the essential DOFs.  The FP32 path keeps the
 // activations for the backward pass; the FP16 path is the fused inference kernel.
-int net_part(pa_lp *lp, const double *r, double *z, hipStream_t s, bool fp16)
+int net_part(pa_lp *lp, const double *r, double *z, hipStream_t s, bool fp16, bool accumulate = false,
+             double scale = 1.0)
 {
     pa_op *op = lp->op;
-    HIP_OK(vec_fill(z, 0.0, lp->ndof, s));
+    if (!accumulate) HIP_OK(vec_fill(z, 0.0, lp->ndof, s));
     if (fp16) {
-        HIP_OK(nn_infer16(lp->n, lp->nelem, lp->params, lp->wpack, r, op->d_elem_dofs, lp->logk, lp->inv_mult, z, s));
+        HIP_OK(nn_infer16(lp->n, lp->nelem, lp->params, lp->wpack, r, op->d_elem_dofs, lp->logk, lp->inv_mult, scale,
+                          z, s));
     } else {
         HIP_OK(nn_input(lp->n, lp->nelem, r, op->d_elem_dofs, lp->logk, lp->x0, lp->s, s));
-        HIP_OK(nn_forward(lp->n, lp->nelem, lp->params, lp->wt, lp->x0, lp->a1, lp->a2, lp->out, s));
-        HIP_OK(nn_output(lp->n, lp->nelem, lp->out, lp->s, op->d_elem_dofs, lp->inv_mult, z, s));
+        HIP_OK(nn_forward(lp->n, 2 * lp->nelem, lp->params, lp->wt, lp->x0, lp->a1, lp->a2, lp->out, s));
+        HIP_OK(nn_output(lp->n, lp->nelem, lp->out, lp->s, op->d_elem_dofs, lp->inv_mult, scale, z, s));
     }
     if (op->ness) HIP_OK(vec_zero_list(z, op->d_ess, op->ness, s));
+    return PA_OK;
+}
+
+// Capture the coarse Jacobi-PCG (2 kernels per iteration) into a graph so that one
+// launch replaces 2k + 1; the kernels clear what they need themselves (no memset nodes).
+int ensure_coarse_graph(pa_lp *lp)
+{
+    if (lp->cexec && lp->cgraph_iters == lp->o.coarse_iters) return PA_OK;
+    lp->free_graph();
+    if (!lp->cap_stream) HIP_OK(hipStreamCreateWithFlags(&lp->cap_stream, hipStreamNonBlocking));
+    HIP_OK(hipStreamBeginCapture(lp->cap_stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t e1 = coarse_pcg(lp->box, lp->S, lp->cdinv, lp->cr, lp->cu, lp->cz, lp->cp0, lp->cp1, lp->cAp,
+                                     lp->cpart, lp->csc, lp->o.coarse_iters, lp->cap_stream);
+    const hipError_t e2 = hipStreamEndCapture(lp->cap_stream, &lp->cgraph);
+    HIP_OK(e1);
+    HIP_OK(e2);
+    HIP_OK(hipGraphInstantiate(&lp->cexec, lp->cgraph, nullptr, nullptr, 0));
+    lp->cgraph_iters = lp->o.coarse_iters;
     return PA_OK;
 }
 
@@ -259,8 +297,9 @@ int coarse_part(pa_lp *lp, const double *r, double *z, bool add, hipStream_t s)
 {
     HIP_OK(coarse_restrict(lp->box, lp->gll, r, lp->cr, s));
     if (lp->ncess) HIP_OK(vec_zero_list(lp->cr, lp->cess, lp->ncess, s));
-    HIP_OK(coarse_pcg(lp->box, lp->S, lp->cdinv, lp->cr, lp->cu, lp->cz, lp->cp0, lp->cp1, lp->cAp, lp->cpart,
-                      lp->csc, lp->o.coarse_iters, s));
+    int rc = ensure_coarse_graph(lp);
+    if (rc) return rc;
+    HIP_OK(hipGraphLaunch(lp->cexec, s));
     HIP_OK(coarse_prolong(lp->box, lp->gll, lp->cu, z, add, s));
     if (lp->op->ness) HIP_OK(vec_zero_list(z, lp->op->d_ess, lp->op->ness, s));
     return PA_OK;
@@ -295,8 +334,8 @@ int loss_grad(pa_lp *lp, const double *r, const double *t, hipStream_t s)
     if (op->ness) HIP_OK(vec_zero_list(gz, op->d_ess, op->ness, s));
     HIP_OK(nn_output_grad(lp->n, lp->nelem, gz, lp->s, op->d_elem_dofs, lp->inv_mult, lp->gout, s));
     HIP_OK(vec_fill_f32(lp->grads, 0.0f, kNetParams, s));
-    HIP_OK(nn_backward(lp->n, lp->nelem, lp->params, lp->x0, lp->a1, lp->a2, lp->gout, lp->ga2, lp->ga1, lp->grads,
-                       lp->wt, lp->partial, s));
+    HIP_OK(nn_backward(lp->n, 2 * lp->nelem, lp->params, lp->x0, lp->a1, lp->a2, lp->gout, lp->ga2, lp->ga1,
+                       lp->grads, lp->wt, lp->partial, s));
     return PA_OK;
 }
 
@@ -386,11 +425,11 @@ extern "C" int pa_lp_logk(pa_lp *lp, float *dev_out)
 
 int hexpa::lp_precondition(pa_lp *lp, const double *r, double *z, hipStream_t s)
 {
+    // Jacobi, plus the network's learned correction
+    HIP_OK(vec_mul(z, lp->dinv, r, lp->ndof, s));
     if (lp->o.use_net) {
-        int rc = net_part(lp, r, z, s, lp->o.infer_fp16 != 0);
+        int rc = net_part(lp, r, z, s, lp->o.infer_fp16 != 0, true, lp->o.net_scale > 0.0 ? lp->o.net_scale : 1.0);
         if (rc) return rc;
-    } else {
-        HIP_OK(vec_mul(z, lp->dinv, r, lp->ndof, s));
     }
     if (lp->o.use_coarse) {
         int rc = coarse_part(lp, r, z, true, s);
@@ -457,6 +496,9 @@ extern "C" int pa_lp_train_step(pa_lp *lp, const double *b, const double *xstar,
     if (rc) return rc;
     HIP_OK(vec_sub(rbuf, b, rbuf, nd, s));
     HIP_OK(vec_sub(tbuf, xstar, xk, nd, s));
+    // the network learns what Jacobi and the coarse correction leave of the error
+    HIP_OK(vec_mul(lp->v0, lp->dinv, rbuf, nd, s));
+    HIP_OK(vec_sub(tbuf, tbuf, lp->v0, nd, s));
     if (lp->o.use_coarse) {
         rc = coarse_part(lp, rbuf, lp->v0, false, s);
         if (rc) return rc;

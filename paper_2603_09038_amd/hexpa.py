@@ -75,7 +75,7 @@ class CgResult(ctypes.Structure):
 class LpOpts(ctypes.Structure):
     _fields_ = [("use_net", ctypes.c_int32), ("use_coarse", ctypes.c_int32), ("coarse_iters", ctypes.c_int32),
                 ("loss", ctypes.c_int32), ("seed", ctypes.c_int32), ("infer_fp16", ctypes.c_int32),
-                ("lr", ctypes.c_double)]
+                ("lr", ctypes.c_double), ("net_scale", ctypes.c_double)]
 
 
 def _load():
@@ -289,9 +289,9 @@ def cg_solve(h, b, x, rtol=1e-8, max_it=10000, mode=PA_CG_JACOBI, check_every=1,
 
 
 def _lp_opts(use_net=True, use_coarse=True, coarse_iters=20, loss=PA_LP_LOSS_ENERGY, seed=0, lr=1e-3,
-             infer_fp16=True):
+             infer_fp16=True, net_scale=1.0):
     return LpOpts(int(bool(use_net)), int(bool(use_coarse)), int(coarse_iters), int(loss), int(seed),
-                  int(bool(infer_fp16)), float(lr))
+                  int(bool(infer_fp16)), float(lr), float(net_scale))
 
 
 def pa_lp_create(h, **opts):

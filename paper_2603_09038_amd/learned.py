@@ -17,11 +17,15 @@ import numpy as np
 
 from . import hexpa
 
-# roughly log-spaced iteration numbers (Fibonacci-like), 0 = the first residual b
+# roughly log-spaced iteration numbers, 0 = the first residual b: for Jacobi-PCG
+# (Fibonacci-like, up to ~1600) and for FCG with the two-level preconditioner (~150)
 CAPTURE_AT = (0, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89, 144, 233, 377, 610, 987, 1597)
+CAPTURE_AT_FCG = (0, 1, 2, 3, 4, 6, 8, 11, 15, 20, 27, 36, 48, 64, 85, 113, 150)
 
 
 def lognormal_operator(mesh, n, p, draw, sigma=1.0, ell=0.1, nfft=128):
+    # nfft: FFT grid of the random field over [0, 2)^3 (128 for the workloads; 64 is a
+    # cheaper field with the same correlation length for tests)
     """PA diffusion operator (Q = p + 2, Dirichlet box boundary) with kappa = exp(sigma g_draw)."""
     import synth
     grid, contrast = synth.lognormal_kappa_grid(draw, sigma=sigma, ell=ell, nfft=nfft)
@@ -31,21 +35,31 @@ def lognormal_operator(mesh, n, p, draw, sigma=1.0, ell=0.1, nfft=128):
     return op
 
 
-def capture_iterates(op, xstar, max_it=1600, capture_at=CAPTURE_AT):
-    """b = A_c x*, and the Jacobi-PCG iterates x_k at the listed k that the solve reaches."""
+def capture_iterates(op, xstar, lp=None, max_it=None, capture_at=None):
+    """b = A_c x*, and the iterates x_k at the listed k that the solve reaches: Jacobi-PCG
+    (lp None) or FCG preconditioned by lp as it is configured (the distribution of
+    residuals the network meets in use)."""
     import torch
     b = op.apply_constrained(xstar)
+    if capture_at is None:
+        capture_at = CAPTURE_AT if lp is None else CAPTURE_AT_FCG
+    if max_it is None:
+        max_it = capture_at[-1] + 1
     cap = torch.empty((len(capture_at), op.ndof), dtype=torch.float64, device="cuda")
     x = torch.zeros_like(b)
-    res = hexpa.cg_solve(op.h, b, x, rtol=1e-10, max_it=max_it, mode=hexpa.PA_CG_JACOBI, capture_at=capture_at,
-                         capture_x=cap, check_every=8, raise_on_fail=False)
+    mode = hexpa.PA_CG_JACOBI if lp is None else hexpa.PA_CG_FCG
+    res = hexpa.cg_solve(op.h, b, x, rtol=1e-10, max_it=max_it, mode=mode, capture_at=capture_at, capture_x=cap,
+                         check_every=8, lp=None if lp is None else lp.h, raise_on_fail=False)
     reached = [j for j, k in enumerate(capture_at) if k <= res["iters"]]
     return b, cap[reached], res
 
 
-def train(lp, mesh, n, p, draws, epochs=1, seed=0, sigma=1.0, log=None):
+def train(lp, mesh, n, p, draws, epochs=1, seed=0, sigma=1.0, log=None, capture="fcg", nfft=128):
     """Train lp's network on the iterates of the given coefficient draws (one operator
-    at a time).  Returns per-step losses and the seconds spent (capture and training)."""
+    at a time): iterates of FCG with the preconditioner as it currently is (capture
+    "fcg"; the untrained network adds nothing, so the first pass sees the two-level
+    method without it) or of Jacobi-PCG ("jacobi").  Returns per-step losses and the
+    seconds spent (capture and training)."""
     import synth
     import torch
     rng = np.random.default_rng([seed, 11])
@@ -53,13 +67,13 @@ def train(lp, mesh, n, p, draws, epochs=1, seed=0, sigma=1.0, log=None):
     for ep in range(epochs):
         for d in draws:
             t0 = time.perf_counter()
-            op = lognormal_operator(mesh, n, p, d, sigma=sigma)
+            op = lognormal_operator(mesh, n, p, d, sigma=sigma, nfft=nfft)
             xstar = torch.tensor(synth.train_solution(op.nodes().cpu().numpy(), d), dtype=torch.float64,
                                  device="cuda")
-            b, xs, _ = capture_iterates(op, xstar)
+            lp.bind(op)
+            b, xs, _ = capture_iterates(op, xstar, lp=lp if capture == "fcg" else None)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            lp.bind(op)
             for j in rng.permutation(xs.shape[0]):
                 losses.append(lp.train_step(b, xstar, xs[j]))
             torch.cuda.synchronize()
@@ -71,7 +85,8 @@ def train(lp, mesh, n, p, draws, epochs=1, seed=0, sigma=1.0, log=None):
     return losses, t_capture, t_train
 
 
-def compare(lp, mesh, n, p, draws, rtol=1e-8, sigma=1.0, coarse_iters=None, max_it=20000, log=None):
+def compare(lp, mesh, n, p, draws, rtol=1e-8, sigma=1.0, coarse_iters=None, max_it=20000, log=None, net_scale=1.0,
+            nfft=128):
     """Iterations and seconds to rtol on held-out draws for (i) Jacobi-PCG, (ii) FCG with
     Jacobi + coarse correction (the preconditioner without the network), (iii) FCG with
     network + coarse correction.  The right-hand side is b = A_c x* with x* the nodal
@@ -80,7 +95,7 @@ def compare(lp, mesh, n, p, draws, rtol=1e-8, sigma=1.0, coarse_iters=None, max_
     import torch
     rows = []
     for d in draws:
-        op = lognormal_operator(mesh, n, p, d, sigma=sigma)
+        op = lognormal_operator(mesh, n, p, d, sigma=sigma, nfft=nfft)
         xstar = torch.tensor(synth.u_manufactured(op.nodes().cpu().numpy()), dtype=torch.float64, device="cuda")
         b = op.apply_constrained(xstar)
         lp.bind(op)
@@ -90,7 +105,7 @@ def compare(lp, mesh, n, p, draws, rtol=1e-8, sigma=1.0, coarse_iters=None, max_
                                        check_every=8, raise_on_fail=False)
         for key, use_net in (("coarse_jacobi", False), ("coarse_net", True)):
             kw = {} if coarse_iters is None else {"coarse_iters": coarse_iters}
-            lp.configure(use_net=use_net, use_coarse=True, **kw)
+            lp.configure(use_net=use_net, use_coarse=True, net_scale=net_scale, **kw)
             x = torch.zeros_like(b)
             row[key] = hexpa.cg_solve(op.h, b, x, rtol=rtol, max_it=max_it, mode=hexpa.PA_CG_FCG, lp=lp.h,
                                       check_every=4, raise_on_fail=False)

@@ -76,6 +76,9 @@ def test_logk_tiles_and_network_forward(hx, p, fp16):
     # positive 1-homogeneity: scaling r by 2^k scales z by 2^k (the normalised input is unchanged)
     z4 = lp.net(_t(4.0 * r)).cpu().numpy()
     np.testing.assert_allclose(z4, 4.0 * z, rtol=1e-6, atol=1e-12 * np.abs(z).max())
+    # and odd: the network enters through its odd part
+    zm = lp.net(_t(-2.0 * r)).cpu().numpy()
+    np.testing.assert_allclose(zm, -2.0 * z, rtol=1e-6, atol=1e-12 * np.abs(z).max())
     lp.close()
     op.close()
 
@@ -94,10 +97,13 @@ def test_loss_and_gradient(hx, p, loss):
     Lr, gr = nn.loss_and_grads(nn.Net(ps), r, t, _oracle_logk(P, coeff), P.elem_dofs, p + 1, op.ndof, ess, Amul=Amul)
     assert abs(L - Lr) <= 2e-5 * abs(Lr), (L, Lr)
     off = 0
+    gall = np.linalg.norm(np.concatenate([q.ravel() for q in gr]))
     for k, gref in enumerate(gr):
         blk = g[off:off + gref.size]
         off += gref.size
-        assert _rel(blk, gref.ravel()) <= 1e-4, (k, _rel(blk, gref.ravel()))
+        # the output bias cancels in the odd part: its gradient is zero up to rounding
+        scale = max(np.linalg.norm(gref), 1e-3 * gall)
+        assert np.linalg.norm(blk - gref.ravel()) <= 1e-4 * scale, (k, np.linalg.norm(blk - gref.ravel()) / scale)
     assert off == g.size
     lp.close()
     op.close()
@@ -116,7 +122,8 @@ def test_adam_step_matches_the_oracle(hx):
     lp.train_step(_t(b), _t(xstar), _t(xk))
     after = lp.params()
     r = b - Ac(xk)
-    t = np.where(ess, 0.0, xstar - xk)
+    dinv = 1.0 / solvers.constrained_diag(P.diag(), ess)
+    t = np.where(ess, 0.0, xstar - xk - dinv * r)
     _, gr = nn.loss_and_grads(nn.Net(ps), r, t, _oracle_logk(P, coeff), P.elem_dofs, p + 1, op.ndof, ess)
     g = np.concatenate([q.ravel() for q in gr])
     p0 = synth.flat_params(ps).astype(np.float64)
@@ -135,10 +142,20 @@ def test_coarse_correction(hx, p):
     mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=50 + p)
     lp = hx.LearnedPreconditioner(op, use_net=False, use_coarse=True, coarse_iters=12)
     r = np.where(ess, 0.0, synth.rand_x(op.ndof, 8))
-    z = lp.coarse(_t(r)).cpu().numpy()
     cl = CoarseLevel(mesh, n, p, coeff)
     zr = cl.correction(r, 12)
-    assert _rel(z, zr) <= 1e-10, _rel(z, zr)
+    # the coarse solve is replayed from a captured graph: every replay, with eager work of
+    # the program in between, must give the same result
+    rt = _t(r)
+    for rep in range(3):
+        z = lp.coarse(rt).cpu().numpy()
+        assert _rel(z, zr) <= 1e-10, (rep, _rel(z, zr))
+        op.apply(rt)
+    # a different iteration count rebuilds the graph
+    lp.configure(use_net=False, use_coarse=True, coarse_iters=5)
+    z5 = lp.coarse(rt).cpu().numpy()
+    assert _rel(z5, cl.correction(r, 5)) <= 1e-10
+    lp.configure(use_net=False, use_coarse=True, coarse_iters=12)
     # the full preconditioner with the network switched off: Jacobi + coarse
     zf = lp.apply(_t(r)).cpu().numpy()
     dinv = 1.0 / solvers.constrained_diag(P.diag(), ess)
@@ -158,7 +175,8 @@ def test_full_preconditioner_with_network(hx):
     z = lp.apply(_t(r)).cpu().numpy()
     zn, _ = nn.precond_nn(nn.Net(ps), r, _oracle_logk(P, coeff), P.elem_dofs, p + 1, op.ndof, ess)
     zc = CoarseLevel(mesh, n, p, coeff).correction(r, 8)
-    assert _rel(z, zn + zc) <= 2e-5
+    zj = np.where(ess, 0.0, r / solvers.constrained_diag(P.diag(), ess))
+    assert _rel(z, zj + zn + zc) <= 2e-5
     lp.close()
     op.close()
 
@@ -182,8 +200,10 @@ def test_fcg_with_jacobi_reproduces_pcg(hx):
     op.close()
 
 
-@pytest.mark.parametrize("use_net", [False])
+@pytest.mark.parametrize("use_net", [False, True])
 def test_fcg_two_level_converges(hx, use_net):
+    """With the default initialisation (zero output layer) the network adds nothing, so
+    both settings are Jacobi + coarse correction; both must converge and beat Jacobi."""
     n, p = 5, 4
     mesh, grid, coeff, op, P, ess = _problem(hx, n, p, seed=80)
     xs = synth.u_manufactured(op.nodes().cpu().numpy())
@@ -198,9 +218,8 @@ def test_fcg_two_level_converges(hx, use_net):
     assert np.linalg.norm(bb - Ac(xx)) <= 1.05e-8 * np.linalg.norm(bb)
     x0 = torch.zeros_like(b)
     rj = hx.cg_solve(op.h, b, x0, rtol=1e-8, max_it=5000, mode=hx.PA_CG_JACOBI)
-    if not use_net:
-        # the coarse correction must pay in iterations over Jacobi alone
-        assert res["iters"] < rj["iters"], (res, rj)
+    # the coarse correction must pay in iterations over Jacobi alone
+    assert res["iters"] < rj["iters"], (res, rj)
     lp.close()
     op.close()
 
@@ -246,3 +265,24 @@ def test_parameter_file_roundtrip(hx, tmp_path):
     np.testing.assert_array_equal(lp.params(), ps)
     lp.close()
     op.close()
+
+
+def test_training_reduces_fcg_iterations(hx):
+    """The gain the learned part must show: after training on the FCG iterates of 16
+    coefficient draws (8^3 elements, p = 4), FCG with the network converges to 1e-8 in
+    fewer iterations than FCG with the same coarse correction and Jacobi alone, on a
+    held-out draw."""
+    from paper_2603_09038_amd import learned
+    n, p = 8, 4
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    op0 = learned.lognormal_operator(mesh, n, p, 0, nfft=64)
+    lp = hx.LearnedPreconditioner(op0, use_net=True, use_coarse=True, coarse_iters=20, lr=1e-3)
+    losses, _, _ = learned.train(lp, mesh, n, p, list(range(16)), capture="fcg", nfft=64)
+    assert np.mean(losses[-16:]) < np.mean(losses[:16])
+    rows = learned.compare(lp, mesh, n, p, [200], nfft=64)
+    r = rows[0]
+    print("held-out draw 200:", {k: r[k]["iters"] for k in ("jacobi", "coarse_jacobi", "coarse_net")})
+    assert r["coarse_net"]["rc"] == 0 and r["coarse_net"]["rel_res_true"] <= 1.05e-8 and not r["coarse_net"]["fallback"]
+    assert r["coarse_net"]["iters"] < r["coarse_jacobi"]["iters"] < r["jacobi"]["iters"]
+    lp.close()
+
