@@ -184,7 +184,7 @@ def run_learned(hexpa, ntrain, nheld, n=32, p=4, weights=None):
     from paper_2603_09038_amd import learned
     mesh = synth.box_mesh(n, perturb=0.1, seed=0)
     op0 = learned.lognormal_operator(mesh, n, p, 0)
-    lp = hexpa.LearnedPreconditioner(op0, use_net=True, use_coarse=True, coarse_iters=20, lr=1e-3)
+    lp = hexpa.LearnedPreconditioner(op0, use_net=True, use_coarse=True, coarse_iters=4, lr=1e-3)
     out = {"workload": f"{n}^3 perturbed hex mesh, p={p}, Q={p + 2}, log-normal kappa draws, Dirichlet",
            "ndof": op0.ndof, "train_draws": ntrain, "held_out_draws": nheld}
     if weights and os.path.exists(weights):

@@ -19,14 +19,14 @@
 #define HEXPA_OVERSUB 1
 #endif
 #ifndef HEXPA_LATE_D
-#define HEXPA_LATE_D 1
+#define HEXPA_LATE_D 0
 #endif
 #ifndef HEXPA_MIN_BLOCKS
 #define HEXPA_MIN_BLOCKS 3
 #endif
 
 #ifndef HEXPA_LDS_BARRIER
-#define HEXPA_LDS_BARRIER 0
+#define HEXPA_LDS_BARRIER 1
 #endif
 
 namespace hexpa {

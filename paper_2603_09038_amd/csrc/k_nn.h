@@ -59,8 +59,10 @@ struct BoxDims {
 };
 // uf (+)= P1 u1: nodal interpolation of the p=1 field at the fine GLL nodes.
 hipError_t coarse_prolong(const BoxDims &b, const double *gll, const double *u1, double *uf, bool add, hipStream_t s);
-// r1 = P1^T rf (gather form, fixed summation order).
-hipError_t coarse_restrict(const BoxDims &b, const double *gll, const double *rf, double *r1, hipStream_t s);
+// r1 = P1^T rf (three separable 1-D passes, fixed summation order); t1, t2 are work arrays
+// of (nx+1)(ny p+1)(nz p+1) and (nx+1)(ny+1)(nz p+1) values.
+hipError_t coarse_restrict(const BoxDims &b, const double *gll, const double *rf, double *r1, double *t1, double *t2,
+                           hipStream_t s);
 // probe vector of class c in {0..26}: 1 where (I mod 3, J mod 3, K mod 3) == c
 hipError_t coarse_probe_vec(const BoxDims &b, int cls, double *v, hipStream_t s);
 // S[i][slot] = (A v_cls)[i] for the neighbour of i in class cls; constrained rows/columns.

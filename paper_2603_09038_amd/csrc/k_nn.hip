@@ -319,31 +319,30 @@ __global__ void k_prolong(BoxDims b, const double *__restrict__ gll, const doubl
     uf[g] = add ? uf[g] + v : v;
 }
 
-// r1[a,b,c] = sum over the fine nodes of the 2x2x2 coarse cells around the vertex of
-// w(I,a) w(J,b) w(K,c) rf[I,J,K]; fixed loop order, no atomics.
-__global__ void k_restrict(BoxDims b, const double *__restrict__ gll, const double *__restrict__ rf,
-                           double *__restrict__ r1)
+// Restriction r1 = P1^T rf, separable: the weight of fine node (I,J,K) at coarse vertex
+// (a,b,c) is w(I,a) w(J,b) w(K,c), so three 1-D passes (x, then y, then z), each summing
+// the at most 2p + 1 fine lattice points whose 1-D weight for a coarse index is nonzero,
+// in a fixed order (no atomics).  Pass `axis` maps in[nz'][ny'][nx'] to out with that
+// axis shortened from M = n p + 1 to n + 1.
+__global__ void k_restrict_axis(int axis, int n, int p, int64_t nx_in, int64_t ny_in, int64_t nz_in,
+                                const double *__restrict__ gll, const double *__restrict__ in,
+                                double *__restrict__ out)
 {
-    const int64_t Mx = (int64_t)b.nx * b.p + 1, My = (int64_t)b.ny * b.p + 1, Mz = (int64_t)b.nz * b.p + 1;
-    const int64_t Cx = b.nx + 1, Cy = b.ny + 1, Cz = b.nz + 1;
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= Cx * Cy * Cz) return;
-    const int64_t a = v % Cx, bb = (v / Cx) % Cy, c = v / (Cx * Cy);
-    const int64_t I0 = max((int64_t)0, (a - 1) * b.p), I1 = min(Mx - 1, (a + 1) * b.p);
-    const int64_t J0 = max((int64_t)0, (bb - 1) * b.p), J1 = min(My - 1, (bb + 1) * b.p);
-    const int64_t K0 = max((int64_t)0, (c - 1) * b.p), K1 = min(Mz - 1, (c + 1) * b.p);
+    const int64_t C = n + 1, M = (int64_t)n * p + 1;
+    const int64_t ox = axis == 0 ? C : nx_in, oy = axis == 1 ? C : ny_in, oz = axis == 2 ? C : nz_in;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ox * oy * oz) return;
+    const int64_t i = idx % ox, j = (idx / ox) % oy, k = idx / (ox * oy);
+    const int64_t a = axis == 0 ? i : (axis == 1 ? j : k);  // coarse index along the axis
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nx_in : nx_in * ny_in);
+    const int64_t base = (axis == 0 ? 0 : i) + nx_in * ((axis == 1 ? 0 : j) + ny_in * (axis == 2 ? 0 : k));
+    const int64_t I0 = max((int64_t)0, (a - 1) * p), I1 = min(M - 1, (a + 1) * p);
     double acc = 0.0;
-    for (int64_t K = K0; K <= K1; ++K) {
-        const double wz = w1d(K, c, b.nz, b.p, gll);
-        if (wz == 0.0) continue;
-        for (int64_t J = J0; J <= J1; ++J) {
-            const double wyz = w1d(J, bb, b.ny, b.p, gll) * wz;
-            if (wyz == 0.0) continue;
-            const double *row = rf + Mx * (J + My * K);
-            for (int64_t I = I0; I <= I1; ++I) acc = fma(w1d(I, a, b.nx, b.p, gll) * wyz, row[I], acc);
-        }
+    for (int64_t I = I0; I <= I1; ++I) {
+        const double w = w1d(I, a, n, p, gll);
+        if (w != 0.0) acc = fma(w, in[base + I * stride], acc);
     }
-    r1[v] = acc;
+    out[idx] = acc;
 }
 
 __global__ void k_probe_vec(BoxDims b, int cls, double *__restrict__ v)
@@ -390,15 +389,17 @@ __global__ void k_dinv_center(int64_t n1, const double *__restrict__ S, double *
 
 // Block sum in a fixed order; the last workgroup to finish adds the per-block partials in
 // block order and hands the total to fin (thread 0 only), then re-arms the counter.
+// Blocks of kCoarseThreads threads (small blocks spread the 27-point stencil over more CUs).
+constexpr int kCoarseThreads = 256;
 template <class F>
 __device__ inline void grid_sum_last(double v, double *partial, unsigned int *count, F fin)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[kCoarseThreads];
     __shared__ int last;
     const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kCoarseThreads / 2; h > 0; h >>= 1) {
         if (t < h) sh[t] += sh[t + h];
         __syncthreads();
     }
@@ -412,11 +413,11 @@ __device__ inline void grid_sum_last(double v, double *partial, unsigned int *co
     if (!last) return;
     __threadfence();
     double a = 0.0;
-    for (int i = t; i < (int)gridDim.x; i += 256)
+    for (int i = t; i < (int)gridDim.x; i += kCoarseThreads)
         a += __hip_atomic_load(partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     sh[t] = a;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kCoarseThreads / 2; h > 0; h >>= 1) {
         if (t < h) sh[t] += sh[t + h];
         __syncthreads();
     }
@@ -427,7 +428,7 @@ __device__ inline void grid_sum_last(double v, double *partial, unsigned int *co
 }
 
 // u = 0, z = dinv r, p0 = 0; rz = r.z, beta = 0
-__global__ __launch_bounds__(256) void k_cpcg_init(int64_t n1, const double *__restrict__ dinv,
+__global__ __launch_bounds__(kCoarseThreads) void k_cpcg_init(int64_t n1, const double *__restrict__ dinv,
                                                    const double *__restrict__ r, double *__restrict__ u,
                                                    double *__restrict__ z, double *__restrict__ p0, double *partial,
                                                    CoarseScalars *sc)
@@ -448,7 +449,7 @@ __global__ __launch_bounds__(256) void k_cpcg_init(int64_t n1, const double *__r
 }
 
 // p1 = z + beta p0; Ap = S (z + beta p0); alpha = rz / (p1 . Ap)
-__global__ __launch_bounds__(256) void k_cpcg_a(BoxDims b, const double *__restrict__ S,
+__global__ __launch_bounds__(kCoarseThreads) void k_cpcg_a(BoxDims b, const double *__restrict__ S,
                                                 const double *__restrict__ z, const double *__restrict__ p0,
                                                 double *__restrict__ p1, double *__restrict__ Ap, double *partial,
                                                 CoarseScalars *sc)
@@ -480,7 +481,7 @@ __global__ __launch_bounds__(256) void k_cpcg_a(BoxDims b, const double *__restr
 }
 
 // u += alpha p1; r -= alpha Ap; z = dinv r; beta = (r.z)_new / rz
-__global__ __launch_bounds__(256) void k_cpcg_b(int64_t n1, const double *__restrict__ dinv,
+__global__ __launch_bounds__(kCoarseThreads) void k_cpcg_b(int64_t n1, const double *__restrict__ dinv,
                                                 const double *__restrict__ p1, const double *__restrict__ Ap,
                                                 double *__restrict__ u, double *__restrict__ r,
                                                 double *__restrict__ z, double *partial, CoarseScalars *sc)
@@ -899,10 +900,14 @@ hipError_t coarse_prolong(const BoxDims &b, const double *gll, const double *u1,
     return hipGetLastError();
 }
 
-hipError_t coarse_restrict(const BoxDims &b, const double *gll, const double *rf, double *r1, hipStream_t s)
+hipError_t coarse_restrict(const BoxDims &b, const double *gll, const double *rf, double *r1, double *t1, double *t2,
+                           hipStream_t s)
 {
-    const int64_t n1 = (int64_t)(b.nx + 1) * (b.ny + 1) * (b.nz + 1);
-    hipLaunchKernelGGL(k_restrict, dim3(nblk(n1)), dim3(256), 0, s, b, gll, rf, r1);
+    const int64_t Mx = (int64_t)b.nx * b.p + 1, My = (int64_t)b.ny * b.p + 1, Mz = (int64_t)b.nz * b.p + 1;
+    const int64_t Cx = b.nx + 1, Cy = b.ny + 1, Cz = b.nz + 1;
+    hipLaunchKernelGGL(k_restrict_axis, dim3(nblk(Cx * My * Mz)), dim3(256), 0, s, 0, b.nx, b.p, Mx, My, Mz, gll, rf, t1);
+    hipLaunchKernelGGL(k_restrict_axis, dim3(nblk(Cx * Cy * Mz)), dim3(256), 0, s, 1, b.ny, b.p, Cx, My, Mz, gll, t1, t2);
+    hipLaunchKernelGGL(k_restrict_axis, dim3(nblk(Cx * Cy * Cz)), dim3(256), 0, s, 2, b.nz, b.p, Cx, Cy, Mz, gll, t2, r1);
     return hipGetLastError();
 }
 
@@ -932,12 +937,12 @@ hipError_t coarse_pcg(const BoxDims &b, const double *S, const double *dinv, dou
                       hipStream_t s)
 {
     const int64_t n1 = (int64_t)(b.nx + 1) * (b.ny + 1) * (b.nz + 1);
-    const unsigned nb = nblk(n1);
-    hipLaunchKernelGGL(k_cpcg_init, dim3(nb), dim3(256), 0, s, n1, dinv, r1, u, z, p0, partial, sc);
+    const unsigned nb = (unsigned)((n1 + kCoarseThreads - 1) / kCoarseThreads);
+    hipLaunchKernelGGL(k_cpcg_init, dim3(nb), dim3(kCoarseThreads), 0, s, n1, dinv, r1, u, z, p0, partial, sc);
     for (int k = 0; k < iters; ++k) {
         double *pin = (k & 1) ? p1 : p0, *pout = (k & 1) ? p0 : p1;
-        hipLaunchKernelGGL(k_cpcg_a, dim3(nb), dim3(256), 0, s, b, S, z, pin, pout, Ap, partial, sc);
-        hipLaunchKernelGGL(k_cpcg_b, dim3(nb), dim3(256), 0, s, n1, dinv, pout, Ap, u, r1, z, partial, sc);
+        hipLaunchKernelGGL(k_cpcg_a, dim3(nb), dim3(kCoarseThreads), 0, s, b, S, z, pin, pout, Ap, partial, sc);
+        hipLaunchKernelGGL(k_cpcg_b, dim3(nb), dim3(kCoarseThreads), 0, s, n1, dinv, pout, Ap, u, r1, z, partial, sc);
     }
     return hipGetLastError();
 }

@@ -36,7 +36,7 @@ struct pa_lp {
     float *ga1 = nullptr, *ga2 = nullptr, *gout = nullptr, *partial = nullptr;
     // coarse level
     double *gll = nullptr, *S = nullptr, *cdinv = nullptr, *cr = nullptr, *cu = nullptr, *cz = nullptr, *cp0 = nullptr,
-           *cp1 = nullptr, *cAp = nullptr, *cpart = nullptr;
+           *cp1 = nullptr, *cAp = nullptr, *cpart = nullptr, *ct1 = nullptr, *ct2 = nullptr;
     int32_t *cess = nullptr;
     int ncess = 0;
     CoarseScalars *csc = nullptr;
@@ -64,11 +64,11 @@ struct pa_lp {
         for (void *p : {(void *)logk, (void *)inv_mult, (void *)dinv, (void *)x0, (void *)s, (void *)a1, (void *)a2,
                         (void *)out, (void *)ga1, (void *)ga2, (void *)gout, (void *)gll, (void *)S, (void *)cdinv,
                         (void *)cr, (void *)cu, (void *)cz, (void *)cp0, (void *)cp1, (void *)cAp, (void *)cpart,
-                        (void *)cess, (void *)csc, (void *)v0, (void *)v1, (void *)v2, (void *)v3,
+                        (void *)cess, (void *)csc, (void *)ct1, (void *)ct2, (void *)v0, (void *)v1, (void *)v2, (void *)v3,
                         (void *)tr_r, (void *)tr_t})
             dfree(p);
         logk = nullptr; inv_mult = dinv = nullptr; x0 = s = a1 = a2 = out = ga1 = ga2 = gout = nullptr;
-        gll = S = cdinv = cr = cu = cz = cp0 = cp1 = cAp = cpart = nullptr;
+        gll = S = cdinv = cr = cu = cz = cp0 = cp1 = cAp = cpart = ct1 = ct2 = nullptr;
         cess = nullptr; csc = nullptr; v0 = v1 = v2 = v3 = tr_r = tr_t = nullptr;
         if (coarse) pa_destroy(coarse);
         coarse = nullptr;
@@ -92,6 +92,7 @@ int check_opts(const pa_lp_opts *o)
     if (o->use_net != 0 && o->use_net != 1) return arg_error("pa_lp: use_net must be 0 or 1");
     if (o->use_coarse != 0 && o->use_coarse != 1) return arg_error("pa_lp: use_coarse must be 0 or 1");
     if (o->use_coarse && o->coarse_iters < 1) return arg_error("pa_lp: coarse_iters must be >= 1");
+    if (o->coarse_iters > 1000) return arg_error("pa_lp: coarse_iters must be <= 1000");
     if (o->loss != PA_LP_LOSS_ENERGY && o->loss != PA_LP_LOSS_L2) return arg_error("pa_lp: unknown loss");
     if (!(o->lr >= 0.0)) return arg_error("pa_lp: lr must be >= 0");
     if (o->infer_fp16 != 0 && o->infer_fp16 != 1) return arg_error("pa_lp: infer_fp16 must be 0 or 1");
@@ -226,8 +227,13 @@ int bind(pa_lp *lp, pa_op *op, hipStream_t s)
     HIP_OK(dalloc(&lp->cp0, n1));
     HIP_OK(dalloc(&lp->cp1, n1));
     HIP_OK(dalloc(&lp->cAp, n1));
-    HIP_OK(dalloc(&lp->cpart, (n1 + 255) / 256));
+    HIP_OK(dalloc(&lp->cpart, (n1 + 255) / 256));  // one partial per coarse block (256 threads)
     HIP_OK(dalloc(&lp->csc, 1));
+    {
+        const int64_t My = (int64_t)op->ny * op->p + 1, Mz = (int64_t)op->nz * op->p + 1;
+        HIP_OK(dalloc(&lp->ct1, (size_t)(op->nx + 1) * My * Mz));
+        HIP_OK(dalloc(&lp->ct2, (size_t)(op->nx + 1) * (op->ny + 1) * Mz));
+    }
     HIP_OK(hipMemset(lp->csc, 0, sizeof(CoarseScalars)));
     HIP_OK(dalloc(&lp->gll, (size_t)op->d));
     HIP_OK(hipMemcpy(lp->gll, op->tab.nodes.data(), (size_t)op->d * sizeof(double), hipMemcpyHostToDevice));
@@ -295,7 +301,7 @@ int ensure_coarse_graph(pa_lp *lp)
 // z (+)= P1 A1^{-1} P1^T r
 int coarse_part(pa_lp *lp, const double *r, double *z, bool add, hipStream_t s)
 {
-    HIP_OK(coarse_restrict(lp->box, lp->gll, r, lp->cr, s));
+    HIP_OK(coarse_restrict(lp->box, lp->gll, r, lp->cr, lp->ct1, lp->ct2, s));
     if (lp->ncess) HIP_OK(vec_zero_list(lp->cr, lp->cess, lp->ncess, s));
     int rc = ensure_coarse_graph(lp);
     if (rc) return rc;

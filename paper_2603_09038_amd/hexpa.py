@@ -288,7 +288,7 @@ def cg_solve(h, b, x, rtol=1e-8, max_it=10000, mode=PA_CG_JACOBI, check_every=1,
             "fallback": r.fallback}
 
 
-def _lp_opts(use_net=True, use_coarse=True, coarse_iters=20, loss=PA_LP_LOSS_ENERGY, seed=0, lr=1e-3,
+def _lp_opts(use_net=True, use_coarse=True, coarse_iters=4, loss=PA_LP_LOSS_ENERGY, seed=0, lr=1e-3,
              infer_fp16=True, net_scale=1.0):
     return LpOpts(int(bool(use_net)), int(bool(use_coarse)), int(coarse_iters), int(loss), int(seed),
                   int(bool(infer_fp16)), float(lr), float(net_scale))
