@@ -63,7 +63,10 @@ struct GroupRegs {
 };
 
 // D of one group into registers: slot s of thread tid is qp entry L = tid + s*kThreads.
-template <class S, class T>
+// EL: the launch passes an element list (only the coloured launches do).  Making it a
+// compile-time property keeps the list loads, and the memory waits their results need,
+// out of every other instance.
+template <class S, bool EL, class T>
 __device__ __forceinline__ void load_qdata(T (&dq)[S::NS][S::NCOMP], const T *__restrict__ qd,
                                            const int32_t *__restrict__ elist, int e0, int nv, int tid)
 {
@@ -72,14 +75,14 @@ __device__ __forceinline__ void load_qdata(T (&dq)[S::NS][S::NCOMP], const T *__
         const int L = tid + s * kThreads;
         const int e = L / S::Q3, r = L - e * S::Q3;
         const bool ok = e < nv;
-        const int64_t ge = ok ? (elist ? elist[e0 + e] : e0 + e) : 0;
+        const int64_t ge = ok ? (EL ? elist[e0 + e] : e0 + e) : 0;
         const T *src = qd + ge * (int64_t)(S::NCOMP * S::Q3) + r;
 #pragma unroll
         for (int c = 0; c < S::NCOMP; ++c) dq[s][c] = ok ? __builtin_nontemporal_load(src + c * S::Q3) : T(0);
     }
 }
 
-template <class S>
+template <class S, bool EL>
 __device__ __forceinline__ void load_map(int32_t (&m)[GroupRegs<S>::NM], const int32_t *__restrict__ emap,
                                          const int32_t *__restrict__ elist, int e0, int nv, int tid)
 {
@@ -89,7 +92,7 @@ __device__ __forceinline__ void load_map(int32_t (&m)[GroupRegs<S>::NM], const i
         const int e = L / S::D3, I = L - e * S::D3;
         int32_t gi = -1;
         if (e < nv) {
-            const int64_t ge = elist ? elist[e0 + e] : e0 + e;
+            const int64_t ge = EL ? elist[e0 + e] : e0 + e;
             gi = emap[ge * S::D3 + I];
         }
         m[s] = gi;
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
     using S = Shape<D, Q, OPS, (int)sizeof(T)>;
     constexpr int E = S::E, D3 = S::D3, Q3 = S::Q3, NS = S::NS, NC = S::NCOMP, NM = GroupRegs<S>::NM;
     constexpr bool M = S::kMass;
+    constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
     __shared__ T bufA[E * S::SZ_A + S::SLACK];
     __shared__ T bufB[E * S::SZ_B + S::SLACK];
     __shared__ int32_t lmap[E * D3];
@@ -168,8 +172,8 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
     T xcur[NM];
     {
         const int e0 = g * E, nv = min(E, nelem - e0);
-        if constexpr (!kLateD) load_qdata<S>(dq, qd, elist, e0, nv, tid);
-        load_map<S>(mcur, emap, elist, e0, nv, tid);
+        if constexpr (!kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
+        load_map<S, EL>(mcur, emap, elist, e0, nv, tid);
         load_x<S>(xcur, mcur, x);
     }
 
@@ -190,9 +194,9 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
             }
         }
         int32_t mnext[NM];
-        load_map<S>(mnext, emap, elist, e0n, nvn, tid);
+        load_map<S, EL>(mnext, emap, elist, e0n, nvn, tid);
         T dnext[kPrefetchD ? NS : 1][NC];
-        if constexpr (kPrefetchD) load_qdata<S>(dnext, qd, elist, e0n, nvn, tid);
+        if constexpr (kPrefetchD) load_qdata<S, EL>(dnext, qd, elist, e0n, nvn, tid);
         lds_barrier();
 
         // forward contractions
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
         lds_barrier();
 
         // D at quadrature points: v = D grad_ref u (symmetric 3x3) and/or v_u = D_m u
-        if constexpr (kLateD) load_qdata<S>(dq, qd, elist, e0, nv, tid);
+        if constexpr (kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int L = tid + s * kThreads;
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
 #pragma unroll
                     for (int c = 0; c < NC; ++c) dq[s][c] = dnext[s][c];
             } else {
-                load_qdata<S>(dq, qd, elist, e0n, nvn, tid);
+                load_qdata<S, EL>(dq, qd, elist, e0n, nvn, tid);
             }
         }
         lds_barrier();
@@ -293,7 +297,10 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
 // So the D stream of the next group overlaps the transposed passes and the forward
 // passes, and the gathers overlap the forward passes, without holding registers.
 #ifndef HEXPA_APPLY_DMA
-#define HEXPA_APPLY_DMA 0
+#define HEXPA_APPLY_DMA 2
+#endif
+#ifndef HEXPA_DMA_MIN_D
+#define HEXPA_DMA_MIN_D 6  // orders p >= 5 (measured faster there; p <= 4 keeps the register kernel)
 #endif
 #ifndef HEXPA_DMA_LDS_BUDGET
 #define HEXPA_DMA_LDS_BUDGET (53 * 1024)
@@ -325,14 +332,19 @@ __device__ __forceinline__ void dma4(const void *src, uint32_t base)
 }
 __device__ __forceinline__ void dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// HEXPA_APPLY_DMA 1: D staged in LDS too (where two elements still fit);
+//                 2: D in registers (loaded after the D-step for the next group).
 template <int D, int Q, int OPS, class T>
 struct DmaShape {
     using B = Shape<D, Q, OPS, (int)sizeof(T)>;
     static constexpr int TB = (int)sizeof(T);
-    static constexpr int PER = TB * (B::SZ_A + B::SZ_B) + 12 * B::D3 + (TB == 8 ? 8 : 4) * B::D3 + TB * B::NCOMP * B::Q3;
+    static constexpr bool DREG = HEXPA_APPLY_DMA == 2;
+    static constexpr int PER = TB * (B::SZ_A + B::SZ_B) + 12 * B::D3 + (TB == 8 ? 8 : 4) * B::D3 +
+                               (DREG ? 0 : TB * B::NCOMP * B::Q3);
     static constexpr int FIXED = TB * 2 * B::SLACK + (int)sizeof(DevTables);
     static constexpr int E = cclamp((HEXPA_DMA_LDS_BUDGET - FIXED) / PER, 1, 32);
-    static constexpr bool ok = HEXPA_APPLY_DMA != 0 && E >= 2 && (B::NCOMP * B::Q3 * TB) % 16 == 0;
+    static constexpr bool ok = HEXPA_APPLY_DMA != 0 && D >= HEXPA_DMA_MIN_D &&
+                               (DREG || (E >= 2 && (B::NCOMP * B::Q3 * TB) % 16 == 0));
 };
 
 template <int D, int Q, int OPS, int EX, bool ATOMIC>
@@ -344,11 +356,13 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
     using T = typename ExT<EX>::T;
     using S = Shape<D, Q, OPS, (int)sizeof(T)>;
     constexpr int E = DmaShape<D, Q, OPS, T>::E, D3 = S::D3, Q3 = S::Q3, NC = S::NCOMP, ED3 = E * D3;
+    constexpr bool DREG = DmaShape<D, Q, OPS, T>::DREG;
     constexpr int NSD = (E * Q3 + kThreads - 1) / kThreads;
     constexpr int TPC = 16 / (int)sizeof(T), CPE = NC * Q3 / TPC, ECH = E * CPE;
     constexpr bool M = S::kMass, WIDE = sizeof(T) == 8;
     constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
-    __shared__ T sD[E * NC * Q3];
+    __shared__ T sD[DREG ? 1 : E * NC * Q3];
+    T dq[DREG ? NSD : 1][NC];
     __shared__ T bufA[E * S::SZ_A + S::SLACK];
     __shared__ T bufB[E * S::SZ_B + S::SLACK];
     __shared__ int32_t mapb[3][ED3];
@@ -405,6 +419,19 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
     };
     auto issue_d = [&](int gg) {
         const int e0 = gg * E, nv = min(E, nelem - e0), nch = nv * CPE;
+        if constexpr (DREG) {  // into registers: slot s of thread tid is qp entry tid + s kThreads
+#pragma unroll
+            for (int s = 0; s < NSD; ++s) {
+                const int L = tid + s * kThreads;
+                const int e = L / Q3, r = L - e * Q3;
+                const bool ok = e < nv;
+                const int64_t ge = ok ? (EL ? elist[e0 + e] : e0 + e) : 0;
+                const T *src = qd + ge * (int64_t)(NC * Q3) + r;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) dq[s][c] = ok ? __builtin_nontemporal_load(src + c * Q3) : T(0);
+            }
+            return;
+        }
         for (int c0 = wave * 64; c0 < ECH; c0 += kThreads) {
             const int ch = c0 + lane;
             const uint32_t base = lds_byte_addr(sD + c0 * TPC);
@@ -471,17 +498,18 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
             if (L < E * Q3) {
                 const int e = L / Q3, r = L - e * Q3;
                 T *V = bufB + e * S::SZ_B + r;
-                const T *Dm = sD + e * NC * Q3 + r;
+                T dv[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) dv[c] = DREG ? dq[DREG ? s : 0][c] : sD[(e * NC + c) * Q3 + r];
                 if constexpr (S::kDiff) {
                     using CH = Chan<Q, M>;
                     const T g0 = V[CH::X], g1 = V[CH::Y], g2 = V[CH::Z];
-                    const T d0 = Dm[0], d1 = Dm[Q3], d2 = Dm[2 * Q3], d3 = Dm[3 * Q3], d4 = Dm[4 * Q3], d5 = Dm[5 * Q3];
-                    V[CH::X] = d0 * g0 + d1 * g1 + d2 * g2;
-                    V[CH::Y] = d1 * g0 + d3 * g1 + d4 * g2;
-                    V[CH::Z] = d2 * g0 + d4 * g1 + d5 * g2;
-                    if constexpr (M) V[CH::V] = Dm[6 * Q3] * V[CH::V];
+                    V[CH::X] = dv[0] * g0 + dv[1] * g1 + dv[2] * g2;
+                    V[CH::Y] = dv[1] * g0 + dv[3] * g1 + dv[4] * g2;
+                    V[CH::Z] = dv[2] * g0 + dv[4] * g1 + dv[5] * g2;
+                    if constexpr (M) V[CH::V] = dv[6] * V[CH::V];
                 } else {
-                    V[0] *= Dm[0];
+                    V[0] *= dv[0];
                 }
             }
         }
