@@ -163,6 +163,10 @@ const char *pa_last_error(void);
 #define PA_CG_FCG 3        /* flexible CG, FCG(1), preconditioned by a pa_lp handle (learned
                               network and/or p = 1 coarse correction); on breakdown it falls
                               back to Jacobi-PCG from the current iterate */
+#define PA_CG_MIXED_FCG 4  /* FP64 flexible CG, FCG(1), whose preconditioner is the inner
+                              mixed-precision solve of MIXED_IR (Jacobi-PCG on FP32 vectors
+                              with the 16-bit-MFMA apply, inner_rtol / inner_max): the outer
+                              recurrence keeps its direction instead of restarting */
 
 typedef struct pa_lp pa_lp;
 

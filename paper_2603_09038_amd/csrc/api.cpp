@@ -724,12 +724,125 @@ static int solve_fcg(pa_op *op, const double *b, double *x, const pa_cg_opts *o,
     return status;
 }
 
+// FP64 FCG(1) whose preconditioner is the inner mixed-precision solve: z = M(r) with
+// M(r) = d / scale, d ~ A^{-1}(scale r) from Jacobi-PCG on FP32 vectors with the 16-bit
+// apply (scale = power of two putting max |r| in [0.5, 1)).
+static int solve_mixed_fcg(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res,
+                           hipStream_t s, double bnorm, PcgWork<double> &w, const double *dinv64)
+{
+    const int64_t n = op->ndof;
+    const bool con = o->constrained != 0;
+    const int fmt = o->lp_fmt;
+    if (fmt != PA_LP_FP16 && fmt != PA_LP_BF16) return arg_error("cg_solve: lp_fmt must be PA_LP_FP16 or PA_LP_BF16");
+    const int inner_max = o->inner_max > 0 ? o->inner_max : 200;
+    const double inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : 1e-2;
+    const int check = o->check_every < 1 ? 1 : o->check_every;
+    int rc = ensure_qdata32(op, s);
+    if (rc) return rc;
+    PcgWork<float> w32;
+    HIP_OK(w32.init(n, inner_max));
+    float *d32 = nullptr, *dinv32 = nullptr;
+    double *z = nullptr, *rold = nullptr, *tmp = nullptr;
+    HIP_OK(dalloc(&d32, n));
+    std::unique_ptr<void, void (*)(void *)> g1(d32, dfree);
+    HIP_OK(dalloc(&dinv32, n));
+    std::unique_ptr<void, void (*)(void *)> g2(dinv32, dfree);
+    HIP_OK(dalloc(&z, n));
+    std::unique_ptr<void, void (*)(void *)> g3(z, dfree);
+    HIP_OK(dalloc(&rold, n));
+    std::unique_ptr<void, void (*)(void *)> g4(rold, dfree);
+    HIP_OK(dalloc(&tmp, 2));
+    std::unique_ptr<void, void (*)(void *)> g5(tmp, dfree);
+    HIP_OK(vec_to_f32(dinv32, dinv64, 1.0, n, s));
+    auto apply32 = [&](const float *p, float *y) -> int {
+        int r2 = do_apply_lp(op, p, y, fmt, s);
+        if (r2) return r2;
+        if (con && op->ness) HIP_OK(vec_set_list(y, 0.0f, op->d_ess, op->ness, s));
+        return PA_OK;
+    };
+    int inner_total = 0;
+    double *hbuf = w32.h_hist;  // pinned scratch for the scale read-back (slots 2, 3 are free here)
+    auto precondition = [&](const double *r, double *zout) -> int {
+        HIP_OK(vec_maxabs(r, n, w.partial, tmp, s));
+        HIP_OK(hipMemcpyAsync(hbuf + 2, tmp, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        const double rmax = hbuf[2];
+        HIP_OK(vec_fill(zout, 0.0, n, s));
+        if (!(rmax > 0.0) || !std::isfinite(rmax)) return PA_OK;
+        int ex = 0;
+        std::frexp(rmax, &ex);
+        const double scale = std::ldexp(1.0, -ex);
+        HIP_OK(vec_to_f32(w32.r, r, scale, n, s));
+        HIP_OK(vec_fill(d32, 0.0f, n, s));
+        HIP_OK(cg_init<float>(nullptr, w32.r, w32.p, dinv32, n, w32.partial, w32.sc, w32.hist, s));
+        HIP_OK(hipMemcpyAsync(hbuf, w32.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        const double rr0 = hbuf[0];
+        int it_in = 0;
+        double rr_in = 0.0;
+        int st = pcg_iterate<float>(apply32, d32, dinv32, n, inner_rtol * inner_rtol * rr0, inner_max, check, w32, s,
+                                    rr0, &it_in, &rr_in);
+        inner_total += it_in;
+        if (st != PA_OK && st != PA_ERR_NOT_CONVERGED && st != PA_ERR_BREAKDOWN) return st;
+        HIP_OK(vec_axpy_f32(zout, 1.0 / scale, d32, n, s));
+        return PA_OK;
+    };
+    // r = b - A x; z = M(r); p = z
+    rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);
+    if (rc) return rc;
+    HIP_OK(cg_init<double>(b, w.r, w.p, nullptr, n, w.partial, w.sc, w.hist, s));
+    HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const double rr0 = w.h_hist[0];
+    const double tol2 = (o->rtol * bnorm) * (o->rtol * bnorm);
+    auto t0 = std::chrono::steady_clock::now();
+    int it = 0, status = PA_OK;
+    double rr = rr0;
+    if (rr0 > tol2) {
+        rc = precondition(w.r, z);
+        if (rc) return rc;
+        HIP_OK(fcg_direction(z, w.r, nullptr, w.p, n, w.partial, w.sc, s));
+        // outer iterations, each checked at once: the inner solve synchronises with the host anyway
+        status = PA_ERR_NOT_CONVERGED;
+        while (it < o->max_it) {
+            ++it;
+            rc = cg_apply(op, con, w.p, w.Ap, s);
+            if (rc) return rc;
+            HIP_OK(cg_alpha<double>(w.p, w.Ap, n, w.partial, w.sc, s));
+            HIP_OK(fcg_update(x, w.r, rold, w.p, w.Ap, n, w.partial, w.sc, w.hist, it, s));
+            HIP_OK(hipMemcpyAsync(w.h_hist, w.hist + 2 * (size_t)it, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            rr = w.h_hist[0];
+            if (w.h_hist[1] != 0.0) { status = PA_ERR_BREAKDOWN; break; }
+            if (rr <= tol2) { status = PA_OK; break; }
+            rc = precondition(w.r, z);
+            if (rc) return rc;
+            HIP_OK(fcg_direction(z, w.r, rold, w.p, n, w.partial, w.sc, s));
+        }
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    res->seconds = std::chrono::duration<double>(t1 - t0).count();
+    res->iters = it;
+    res->inner_iters_total = inner_total;
+    res->rel_res_recursive = std::sqrt(rr) / bnorm;
+    double trel = 0.0;
+    rc = true_residual(op, con, b, x, w.Ap, w.r, w, bnorm, s, &trel);
+    if (rc) return rc;
+    res->rel_res_true = trel;
+    res->status = status;
+    if (status == PA_ERR_NOT_CONVERGED) set_error("cg_solve: max_it outer iterations reached before rtol");
+    if (status == PA_ERR_BREAKDOWN) set_error("cg_solve: breakdown in the mixed-precision FCG");
+    return status;
+}
+
 extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res, void *stream)
 {
     PA_TRY
     if (!op || !b || !x || !o || !res) return arg_error("cg_solve: NULL argument");
     if (!(o->rtol > 0.0) || o->max_it < 1) return arg_error("cg_solve: need rtol > 0 and max_it >= 1");
-    if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI && o->mode != PA_CG_MIXED_IR && o->mode != PA_CG_FCG)
+    if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI && o->mode != PA_CG_MIXED_IR && o->mode != PA_CG_FCG &&
+        o->mode != PA_CG_MIXED_FCG)
         return arg_error("cg_solve: unknown mode");
     if (o->n_capture < 0 ||
         (o->n_capture > 0 && ((o->mode != PA_CG_JACOBI && o->mode != PA_CG_FCG) || !o->capture_at || !o->capture_x)))
@@ -744,6 +857,7 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     const int check = o->check_every < 1 ? 1 : o->check_every;
     PcgWork<double> w;
     HIP_OK(w.init(n, o->mode == PA_CG_MIXED_IR ? 4 : o->max_it));
+    if (o->mode == PA_CG_MIXED_FCG && !(o->max_it >= 1)) return arg_error("cg_solve: max_it must be >= 1");
     double *dinv = nullptr;
     std::unique_ptr<void, void (*)(void *)> gd(nullptr, dfree);
     if (o->mode != PA_CG_PLAIN) {  // Jacobi (also the inner preconditioner of MIXED_IR)
@@ -767,6 +881,7 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     }
     if (o->mode == PA_CG_MIXED_IR) return solve_mixed_ir(op, b, x, o, res, s, bnorm, w, dinv);
     if (o->mode == PA_CG_FCG) return solve_fcg(op, b, x, o, res, s, bnorm, w, dinv);
+    if (o->mode == PA_CG_MIXED_FCG) return solve_mixed_fcg(op, b, x, o, res, s, bnorm, w, dinv);
 
     // r = b - A x, p = M^{-1} r
     int rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);

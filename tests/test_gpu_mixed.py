@@ -88,8 +88,9 @@ def test_lp_apply_accuracy(hx, p, ops, fmt):
     op.close()
 
 
+@pytest.mark.parametrize("outer", ["ir", "fcg"])
 @pytest.mark.parametrize("fmt", [0, 1])
-def test_mixed_ir_reaches_fp64_tolerance(hx, fmt):
+def test_mixed_ir_reaches_fp64_tolerance(hx, fmt, outer):
     """Log-normal coefficient (sigma = 1, correlation length 0.1), p = 6, Q = 8, Dirichlet,
     b = A_c x* with x* the nodal interpolant of sin(pi x) sin(pi y) sin(pi z)."""
     import torch
@@ -100,8 +101,8 @@ def test_mixed_ir_reaches_fp64_tolerance(hx, fmt):
     xs = synth.u_manufactured(op.nodes().cpu().numpy())
     b = op.apply_constrained(_t(xs))
     x = torch.zeros_like(b)
-    res = hx.cg_solve(op.h, b, x, rtol=1e-10, max_it=60, mode=hx.PA_CG_MIXED_IR, lp_fmt=fmt, inner_rtol=1e-2,
-                      inner_max=400)
+    mode = hx.PA_CG_MIXED_IR if outer == "ir" else hx.PA_CG_MIXED_FCG
+    res = hx.cg_solve(op.h, b, x, rtol=1e-10, max_it=60, mode=mode, lp_fmt=fmt, inner_rtol=1e-2, inner_max=400)
     assert res["rc"] == 0 and res["rel_res_true"] <= 1e-10, res
     P = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.from_grid(grid), ops=oracle.DIFFUSION)
     Ac = solvers.constrained(P.apply, oracle.box_boundary(n, p).astype(bool))
