@@ -23,16 +23,20 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+# the translation unit of the apply kernels (its own sources and the build flags)
+APPLY_SOURCES = ("csrc/k_apply.hip", "csrc/apply_passes.h", "csrc/apply_common.h", "csrc/internal.h",
+                 "../include/hexpa.h", "build.py")
+
+
 def kernel_source_hash():
-    """SHA-256 over the HIP sources of the library (traffic figures are tied to it)."""
+    """SHA-256 over the sources the apply kernels are compiled from (traffic figures are
+    tied to it)."""
     import hashlib
-    d = os.path.join(ROOT, "paper_2603_09038_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(f.read())
+    for name in APPLY_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2603_09038_amd", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
