@@ -301,31 +301,29 @@ __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevT
 // pinned by test_mfma_16bit_lane_layouts.  Used by the mixed-precision inner apply: the
 // LDS tensors hold FP32 values that are rounded to FP16/BF16 as they enter the MFMA,
 // and the products accumulate in FP32.
+// The B-operand needs no masking: a lane whose k lies past the pass's K reads a real
+// (finite) value of its own column, and the A-operand is zero there; a padding column
+// (past NCOL, or an idle tile) may read stale LDS, but GEMM columns are independent and
+// those outputs are never stored.
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float flt4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ short f32_to_bf16_rne(float f)
-{
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return (short)(u >> 16);
-}
+typedef float flt2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
 
 template <bool BF>
 struct Mfma16 {
     using V = typename std::conditional<BF, bf16x4_t, half4_t>::type;
+    // four FP32 values rounded to nearest-even 16-bit, two per v_cvt_pk_{bf16,f16}_f32
     __device__ static __forceinline__ V pack(const float (&f)[4])
     {
-        V v;
-        if constexpr (BF) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) v[t] = f32_to_bf16_rne(f[t]);
-        } else {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) v[t] = (_Float16)f[t];
-        }
-        return v;
+        using H2 = typename std::conditional<BF, bf16x2_t, half2_t>::type;
+        const H2 lo = __builtin_convertvector((flt2_t{f[0], f[1]}), H2);
+        const H2 hi = __builtin_convertvector((flt2_t{f[2], f[3]}), H2);
+        const u32x2_t w = {__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)};
+        return __builtin_bit_cast(V, w);
     }
     __device__ static __forceinline__ flt4_t mma(V a, V b, flt4_t c)
     {
@@ -405,10 +403,7 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
             for (int kc = 0; kc < KC; ++kc) {
                 float f[4];
 #pragma unroll
-                for (int t4 = 0; t4 < 4; ++t4) {
-                    const float v = base[lin[kc][t4]];
-                    f[t4] = (cv[bi] && kval[kc][t4]) ? v : 0.0f;
-                }
+                for (int t4 = 0; t4 < 4; ++t4) f[t4] = base[lin[kc][t4]];
                 bv[bi][kc] = Mfma16<BF>::pack(f);
             }
         }

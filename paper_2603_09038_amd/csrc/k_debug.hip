@@ -6,12 +6,11 @@
 // The tests read off which entry of the product each lane/element holds.
 #include <hip/hip_runtime.h>
 
-#include "internal.h"
+#include "apply_common.h"
 
 namespace hexpa {
 
 namespace {
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(64) void k_debug_mfma(const double *__restrict__ A, const double *__restrict__ B,
                                                    double *__restrict__ Draw)
@@ -33,39 +32,20 @@ __global__ __launch_bounds__(64) void k_debug_mfma4(const double *__restrict__ A
     const double b = B[beta * 16 + (l >> 4) * 4 + (l & 3)];
     Draw[l] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, 0.0, 0, 0, 0);
 }
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
-typedef float flt4_t __attribute__((ext_vector_type(4)));
-
-__device__ short to_bf16_rne(float f)
-{
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
 
 // v_mfma_f32_16x16x16{f16,bf16}: lane l supplies A[l%16][4(l/16)+t], B[4(l/16)+t][l%16].
+// The operands go through the apply kernels' own rounding (Mfma16<BF>::pack) and MFMA.
 template <bool BF>
 __global__ __launch_bounds__(64) void k_debug_mfma16(const float *__restrict__ A, const float *__restrict__ B,
                                                      float *__restrict__ Draw)
 {
     const int l = threadIdx.x;
-    flt4_t acc = {0.f, 0.f, 0.f, 0.f};
-    if constexpr (BF) {
-        bf16x4_t a, b;
-        for (int t = 0; t < 4; ++t) {
-            a[t] = to_bf16_rne(A[(l % 16) * 16 + 4 * (l / 16) + t]);
-            b[t] = to_bf16_rne(B[(4 * (l / 16) + t) * 16 + l % 16]);
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    } else {
-        half4_t a, b;
-        for (int t = 0; t < 4; ++t) {
-            a[t] = (_Float16)A[(l % 16) * 16 + 4 * (l / 16) + t];
-            b[t] = (_Float16)B[(4 * (l / 16) + t) * 16 + l % 16];
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+    float fa[4], fb[4];
+    for (int t = 0; t < 4; ++t) {
+        fa[t] = A[(l % 16) * 16 + 4 * (l / 16) + t];
+        fb[t] = B[(4 * (l / 16) + t) * 16 + l % 16];
     }
+    const flt4_t acc = Mfma16<BF>::mma(Mfma16<BF>::pack(fa), Mfma16<BF>::pack(fb), flt4_t{0.f, 0.f, 0.f, 0.f});
     for (int v = 0; v < 4; ++v) Draw[4 * l + v] = acc[v];
 }
 }  // namespace
