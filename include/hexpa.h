@@ -167,6 +167,11 @@ const char *pa_last_error(void);
                               mixed-precision solve of MIXED_IR (Jacobi-PCG on FP32 vectors
                               with the 16-bit-MFMA apply, inner_rtol / inner_max): the outer
                               recurrence keeps its direction instead of restarting */
+#define PA_CG_MIXED_RU 5   /* one Jacobi-PCG recurrence on FP32 vectors with the 16-bit-MFMA
+                              apply, never restarted; at most every inner_max iterations its
+                              residual is replaced by the FP64 residual b - A x and the FP32
+                              correction is added to x in FP64 (reliable updates); max_it
+                              bounds the total iterations; iters reports the replacements */
 
 typedef struct pa_lp pa_lp;
 

@@ -724,6 +724,116 @@ static int solve_fcg(pa_op *op, const double *b, double *x, const pa_cg_opts *o,
     return status;
 }
 
+// One Jacobi-PCG recurrence on FP32 vectors with the 16-bit apply, never restarted;
+// every few iterations its residual is replaced by the true FP64 residual ("reliable
+// updates", Sleijpen & van der Vorst 1996): x += xh / scale (the FP32 update accumulated
+// since the last replacement), r = b - A x in FP64, rh = scale' r with a new power-of-two
+// scale, and the direction continues from the old one rescaled by scale' / scale (the
+// next beta uses the replaced residual).  Replacement k + 1 comes after a chunk of
+// iterations predicted from the convergence rate so far, at most inner_max.
+static int solve_mixed_ru(pa_op *op, const double *b, double *x, const pa_cg_opts *o, pa_cg_result *res,
+                          hipStream_t s, double bnorm, PcgWork<double> &w64, const double *dinv64)
+{
+    const int64_t n = op->ndof;
+    const bool con = o->constrained != 0;
+    const int fmt = o->lp_fmt;
+    if (fmt != PA_LP_FP16 && fmt != PA_LP_BF16) return arg_error("cg_solve: lp_fmt must be PA_LP_FP16 or PA_LP_BF16");
+    if (!dinv64) return arg_error("cg_solve: MIXED_RU needs the Jacobi diagonal");
+    const int kmax = o->inner_max > 0 ? o->inner_max : 100;
+    const int max_total = o->max_it;
+    int rc = ensure_qdata32(op, s);
+    if (rc) return rc;
+    PcgWork<float> w32;
+    HIP_OK(w32.init(n, max_total + 2));
+    float *xh = nullptr, *dinv32 = nullptr;
+    HIP_OK(dalloc(&xh, n));
+    std::unique_ptr<void, void (*)(void *)> g1(xh, dfree);
+    HIP_OK(dalloc(&dinv32, n));
+    std::unique_ptr<void, void (*)(void *)> g2(dinv32, dfree);
+    HIP_OK(vec_to_f32(dinv32, dinv64, 1.0, n, s));
+    CgScalars *hsc = nullptr;
+    HIP_OK(hipHostMalloc((void **)&hsc, sizeof(CgScalars), hipHostMallocDefault));
+    std::unique_ptr<void, hipError_t (*)(void *)> g3(hsc, hipHostFree);
+    // true residual r64 = b - A x (in w64.Ap), its norm and max-abs (host)
+    auto true_res = [&](double *rel, double *rmax) -> int {
+        int r2 = con ? do_apply_constrained(op, x, w64.Ap, s) : do_apply(op, op->variant, x, w64.Ap, s);
+        if (r2) return r2;
+        HIP_OK(cg_init<double>(b, w64.Ap, nullptr, nullptr, n, w64.partial, w64.sc, w64.hist, s));
+        HIP_OK(vec_maxabs(w64.Ap, n, w64.partial, w64.tmp, s));
+        HIP_OK(hipMemcpyAsync(w64.h_hist, w64.hist, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(w64.h_hist + 1, w64.tmp, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipMemcpyAsync(hsc, w32.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        *rel = std::sqrt(w64.h_hist[0]) / bnorm;
+        *rmax = w64.h_hist[1];
+        return PA_OK;
+    };
+    auto pow2_scale = [](double rmax) {
+        int ex = 0;
+        std::frexp(rmax, &ex);
+        return std::ldexp(1.0, -ex);
+    };
+    auto t0 = std::chrono::steady_clock::now();
+    int status = PA_ERR_NOT_CONVERGED, total = 0, replacements = 0;
+    double rel = 0.0, rmax = 0.0;
+    static_assert(sizeof(CgScalars) % sizeof(double) == 0, "CgScalars is cleared as doubles");
+    HIP_OK(vec_fill(reinterpret_cast<double *>(w32.sc), 0.0, sizeof(CgScalars) / sizeof(double), s));  // rz = 0
+    if ((rc = true_res(&rel, &rmax))) return rc;
+    if (!std::isfinite(rel)) status = PA_ERR_BREAKDOWN;
+    else if (rel <= o->rtol) status = PA_OK;
+    double scale = 1.0, rel_prev = rel;
+    int chunk_prev = 0, k = kmax;
+    bool first = true;
+    while (status == PA_ERR_NOT_CONVERGED && total < max_total) {
+        // replace the recursive residual: rh = scale' r64, direction rescaled by scale' / scale
+        const double ns = pow2_scale(rmax);
+        const double f = first ? 1.0 : ns / scale;
+        HIP_OK(vec_to_f32(w32.r, w64.Ap, ns, n, s));
+        HIP_OK(vec_fill(xh, 0.0f, n, s));
+        HIP_OK(cg_rz_partials<float>(w32.r, dinv32, n, w32.partial, s));
+        HIP_OK(cg_update_dir<float>(w32.p, w32.r, dinv32, n, w32.partial, w32.sc, w32.hist, total, f, s));
+        scale = ns;
+        first = false;
+        // chunk length from the observed rate (iterations per factor of reduction)
+        if (chunk_prev > 0 && rel < rel_prev && rel_prev > 0.0) {
+            const double per_it = std::log(rel / rel_prev) / chunk_prev;  // < 0
+            const int need = (int)std::ceil(std::log(o->rtol / rel) / per_it);
+            k = std::max(8, std::min(kmax, need + 2));
+        }
+        k = std::min(k, max_total - total);
+        for (int j = 1; j <= k; ++j) {
+            rc = do_apply_lp(op, w32.p, w32.Ap, fmt, s);
+            if (rc) return rc;
+            if (con && op->ness) HIP_OK(vec_set_list(w32.Ap, 0.0f, op->d_ess, op->ness, s));
+            HIP_OK(cg_alpha<float>(w32.p, w32.Ap, n, w32.partial, w32.sc, s));
+            HIP_OK(cg_update_xr<float>(xh, w32.r, w32.p, w32.Ap, dinv32, n, w32.partial, w32.sc, s));
+            if (j < k)
+                HIP_OK(cg_update_dir<float>(w32.p, w32.r, dinv32, n, w32.partial, w32.sc, w32.hist, total + j, 1.0, s));
+        }
+        total += k;
+        HIP_OK(vec_axpy_f32(x, 1.0 / scale, xh, n, s));
+        rel_prev = rel;
+        chunk_prev = k;
+        ++replacements;
+        if ((rc = true_res(&rel, &rmax))) return rc;
+        if (!std::isfinite(rel) || hsc->breakdown) { status = PA_ERR_BREAKDOWN; break; }
+        if (rel <= o->rtol) status = PA_OK;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    res->seconds = std::chrono::duration<double>(t1 - t0).count();
+    res->iters = replacements;
+    res->inner_iters_total = total;
+    res->rel_res_recursive = rel;
+    double trel = 0.0;
+    rc = true_residual(op, con, b, x, w64.Ap, w64.r, w64, bnorm, s, &trel);
+    if (rc) return rc;
+    res->rel_res_true = trel;
+    res->status = status;
+    if (status == PA_ERR_NOT_CONVERGED) set_error("cg_solve: max_it iterations reached before rtol");
+    if (status == PA_ERR_BREAKDOWN) set_error("cg_solve: breakdown in the reliable-update mixed-precision CG");
+    return status;
+}
+
 // FP64 FCG(1) whose preconditioner is the inner mixed-precision solve: z = M(r) with
 // M(r) = d / scale, d ~ A^{-1}(scale r) from Jacobi-PCG on FP32 vectors with the 16-bit
 // apply (scale = power of two putting max |r| in [0.5, 1)).
@@ -842,7 +952,7 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     if (!op || !b || !x || !o || !res) return arg_error("cg_solve: NULL argument");
     if (!(o->rtol > 0.0) || o->max_it < 1) return arg_error("cg_solve: need rtol > 0 and max_it >= 1");
     if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI && o->mode != PA_CG_MIXED_IR && o->mode != PA_CG_FCG &&
-        o->mode != PA_CG_MIXED_FCG)
+        o->mode != PA_CG_MIXED_FCG && o->mode != PA_CG_MIXED_RU)
         return arg_error("cg_solve: unknown mode");
     if (o->n_capture < 0 ||
         (o->n_capture > 0 && ((o->mode != PA_CG_JACOBI && o->mode != PA_CG_FCG) || !o->capture_at || !o->capture_x)))
@@ -882,6 +992,7 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     if (o->mode == PA_CG_MIXED_IR) return solve_mixed_ir(op, b, x, o, res, s, bnorm, w, dinv);
     if (o->mode == PA_CG_FCG) return solve_fcg(op, b, x, o, res, s, bnorm, w, dinv);
     if (o->mode == PA_CG_MIXED_FCG) return solve_mixed_fcg(op, b, x, o, res, s, bnorm, w, dinv);
+    if (o->mode == PA_CG_MIXED_RU) return solve_mixed_ru(op, b, x, o, res, s, bnorm, w, dinv);
 
     // r = b - A x, p = M^{-1} r
     int rc = con ? do_apply_constrained(op, x, w.r, s) : do_apply(op, op->variant, x, w.r, s);

@@ -191,12 +191,11 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
             eS[bi] = e;
             n0S[bi] = n0;
             cv[bi] = tv && (n0 + nl < P::NCOL);
+            // no masking needed: past K a lane reads a finite value of its own column
+            // (A is zero there); padding columns are independent and never stored
             const double *base = in + e * szin + n0 * C;
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const double v = base[lin[kc]];
-                bv[bi][kc] = (cv[bi] && kval[kc]) ? v : 0.0;
-            }
+            for (int kc = 0; kc < KC; ++kc) bv[bi][kc] = base[lin[kc]];
         }
         double acc[BATCH][RT];
 #pragma unroll

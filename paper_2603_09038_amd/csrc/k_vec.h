@@ -34,6 +34,20 @@ template <class T>
 hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
                      double *hist, int it, hipStream_t s);
 
+// The two halves of cg_update, for solvers that act between them:
+// x += alpha p, r -= alpha Ap, partial sums of (r . dinv r, r . r)
+template <class T>
+hipError_t cg_update_xr(T *x, T *r, const T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
+                        hipStream_t s);
+// the same partial sums for a given r (after it has been replaced)
+template <class T>
+hipError_t cg_rz_partials(const T *r, const T *dinv, int64_t n, double *partial, hipStream_t s);
+// beta = rz_new / (rz f), rz = rz_new, p = dinv r + beta p; hist as cg_update.  f: factor by
+// which r and p were rescaled since rz was taken (1 if they were not)
+template <class T>
+hipError_t cg_update_dir(T *p, const T *r, const T *dinv, int64_t n, double *partial, CgScalars *sc, double *hist,
+                         int it, double f, hipStream_t s);
+
 // ------------------------------------------------------------------ FCG vectors
 // x += alpha p; rold = r; r -= alpha Ap; hist[2 it] = r.r, hist[2 it + 1] = breakdown
 hipError_t fcg_update(double *x, double *r, double *rold, const double *p, const double *Ap, int64_t n,

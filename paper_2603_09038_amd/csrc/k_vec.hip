@@ -141,8 +141,10 @@ __global__ void k_cg_update1(T *__restrict__ x, T *__restrict__ r, const T *__re
     }
 }
 
-// beta = rz_new / rz; rz = rz_new; record ||r||^2 for iteration `it`.
-__global__ void k_cg_beta(const double *partial, int nb, CgScalars *s, double *rr_hist, int it)
+// beta = rz_new / (rz f); rz = rz_new; record ||r||^2 for iteration `it`.  f != 1 when
+// the vectors were rescaled by f since rz was taken (rz scales by f^2, the old direction
+// p by f: folding one f into beta rescales p inside the direction update).
+__global__ void k_cg_beta(const double *partial, int nb, CgScalars *s, double *rr_hist, int it, double f)
 {
     __shared__ double sh[2 * 256];
     double v[2] = {0.0, 0.0};
@@ -154,7 +156,7 @@ __global__ void k_cg_beta(const double *partial, int nb, CgScalars *s, double *r
     if (threadIdx.x == 0) {
         const double rz_new = v[0];
         if (!isfinite(rz_new) || !isfinite(v[1])) s->breakdown = 1;
-        s->beta = (s->rz != 0.0) ? rz_new / s->rz : 0.0;
+        s->beta = (s->rz != 0.0) ? rz_new / (s->rz * f) : 0.0;
         s->rz = rz_new;
         s->rr = v[1];
         rr_hist[2 * it] = v[1];
@@ -174,8 +176,8 @@ __global__ void k_cg_update2(T *__restrict__ p, const T *__restrict__ r, const T
     }
 }
 
-// r = b - r_in (r holds A x on entry; b == nullptr means x = 0, r = r_in unchanged ... ) and
-// partial sums of r . dinv r and r . r; p = dinv r.
+// r = b - r_in (r holds A x on entry; b == nullptr: r unchanged) and partial sums of
+// r . dinv r and r . r; p = dinv r (p == nullptr: not written).
 template <class T>
 __global__ void k_cg_init(const T *__restrict__ b, T *__restrict__ r, T *__restrict__ p, const T *__restrict__ dinv,
                           int64_t n, double *partial)
@@ -186,7 +188,7 @@ __global__ void k_cg_init(const T *__restrict__ b, T *__restrict__ r, T *__restr
         const T ri = b ? (T)(b[i] - r[i]) : r[i];
         r[i] = ri;
         const T zi = dinv ? dinv[i] * ri : ri;
-        p[i] = zi;
+        if (p) p[i] = zi;
         v[0] = fma((double)ri, (double)zi, v[0]);
         v[1] = fma((double)ri, (double)ri, v[1]);
     }
@@ -399,7 +401,29 @@ hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, do
                      double *hist, int it, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cg_update1<T>, dim3(kRedBlocks), dim3(256), 0, s, x, r, p, Ap, dinv, n, sc, partial);
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc, hist, it);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc, hist, it, 1.0);
+    hipLaunchKernelGGL(k_cg_update2<T>, dim3(kRedBlocks), dim3(256), 0, s, p, r, dinv, n, sc);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t cg_update_xr(T *x, T *r, const T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_update1<T>, dim3(kRedBlocks), dim3(256), 0, s, x, r, p, Ap, dinv, n, sc, partial);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t cg_rz_partials(const T *r, const T *dinv, int64_t n, double *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(kRedBlocks), dim3(256), 0, s, nullptr, const_cast<T *>(r), nullptr, dinv, n,
+                       partial);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t cg_update_dir(T *p, const T *r, const T *dinv, int64_t n, double *partial, CgScalars *sc, double *hist,
+                         int it, double f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc, hist, it, f);
     hipLaunchKernelGGL(k_cg_update2<T>, dim3(kRedBlocks), dim3(256), 0, s, p, r, dinv, n, sc);
     return hipGetLastError();
 }
@@ -408,7 +432,12 @@ hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, do
                                    hipStream_t);                                                               \
     template hipError_t cg_alpha<T>(const T *, const T *, int64_t, double *, CgScalars *, hipStream_t);         \
     template hipError_t cg_update<T>(T *, T *, T *, const T *, const T *, int64_t, double *, CgScalars *,      \
-                                     double *, int, hipStream_t);
+                                     double *, int, hipStream_t);                                              \
+    template hipError_t cg_update_xr<T>(T *, T *, const T *, const T *, const T *, int64_t, double *,          \
+                                        CgScalars *, hipStream_t);                                             \
+    template hipError_t cg_rz_partials<T>(const T *, const T *, int64_t, double *, hipStream_t);              \
+    template hipError_t cg_update_dir<T>(T *, const T *, const T *, int64_t, double *, CgScalars *, double *,  \
+                                         int, double, hipStream_t);
 HEXPA_INST(double)
 HEXPA_INST(float)
 

@@ -88,8 +88,7 @@ def test_lp_apply_accuracy(hx, p, ops, fmt):
     op.close()
 
 
-@pytest.mark.parametrize("outer", ["ir", "fcg"])
-@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("outer,fmt", [("ir", 0), ("ir", 1), ("fcg", 0), ("fcg", 1), ("ru", 0)])
 def test_mixed_ir_reaches_fp64_tolerance(hx, fmt, outer):
     """Log-normal coefficient (sigma = 1, correlation length 0.1), p = 6, Q = 8, Dirichlet,
     b = A_c x* with x* the nodal interpolant of sin(pi x) sin(pi y) sin(pi z)."""
@@ -101,8 +100,11 @@ def test_mixed_ir_reaches_fp64_tolerance(hx, fmt, outer):
     xs = synth.u_manufactured(op.nodes().cpu().numpy())
     b = op.apply_constrained(_t(xs))
     x = torch.zeros_like(b)
-    mode = hx.PA_CG_MIXED_IR if outer == "ir" else hx.PA_CG_MIXED_FCG
-    res = hx.cg_solve(op.h, b, x, rtol=1e-10, max_it=60, mode=mode, lp_fmt=fmt, inner_rtol=1e-2, inner_max=400)
+    if outer == "ru":  # reliable updates: max_it bounds the total iterations, inner_max the period
+        res = hx.cg_solve(op.h, b, x, rtol=1e-10, max_it=3000, mode=hx.PA_CG_MIXED_RU, lp_fmt=fmt, inner_max=40)
+    else:
+        mode = hx.PA_CG_MIXED_IR if outer == "ir" else hx.PA_CG_MIXED_FCG
+        res = hx.cg_solve(op.h, b, x, rtol=1e-10, max_it=60, mode=mode, lp_fmt=fmt, inner_rtol=1e-2, inner_max=400)
     assert res["rc"] == 0 and res["rel_res_true"] <= 1e-10, res
     P = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.from_grid(grid), ops=oracle.DIFFUSION)
     Ac = solvers.constrained(P.apply, oracle.box_boundary(n, p).astype(bool))
