@@ -422,12 +422,13 @@ static int ensure_qdata32(pa_op *op, hipStream_t s)
     return PA_OK;
 }
 
-static int do_apply_lp(pa_op *op, const float *x, float *y, int fmt, hipStream_t s)
+// y = A x with the 16-bit apply; zero_first = false: y already holds zeros (or a sum to add to)
+static int do_apply_lp(pa_op *op, const float *x, float *y, int fmt, hipStream_t s, bool zero_first = true)
 {
     int rc = ensure_qdata32(op, s);
     if (rc) return rc;
     bool ok = true;
-    HIP_OK(vec_fill(y, 0.0f, op->ndof, s));
+    if (zero_first) HIP_OK(vec_fill(y, 0.0f, op->ndof, s));
     HIP_OK(launch_apply_lp(op, fmt, x, y, s, &ok));
     if (!ok) {
         set_error("mixed-precision apply not instantiated for this (p, q1d, ops)");
@@ -452,7 +453,7 @@ namespace {
 template <class T>
 struct PcgWork {
     T *r = nullptr, *p = nullptr, *Ap = nullptr;
-    double *partial = nullptr, *hist = nullptr, *tmp = nullptr;
+    double *partial = nullptr, *partial2 = nullptr, *hist = nullptr, *tmp = nullptr;
     CgScalars *sc = nullptr;
     double *h_hist = nullptr;  // pinned: 2 slots x (r.r, breakdown)
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -462,6 +463,7 @@ struct PcgWork {
         max_it = max_it_;
         hipError_t e;
         if ((e = dalloc(&r, n)) || (e = dalloc(&p, n)) || (e = dalloc(&Ap, n)) || (e = dalloc(&partial, 2 * kRedBlocks)) ||
+            (e = dalloc(&partial2, 2 * kRedBlocks)) ||
             (e = dalloc(&hist, 2 * ((size_t)max_it + 2))) || (e = dalloc(&tmp, 4)) || (e = dalloc(&sc, 1)))
             return e;
         if ((e = hipHostMalloc((void **)&h_hist, 4 * sizeof(double), hipHostMallocDefault))) return e;
@@ -470,7 +472,7 @@ struct PcgWork {
     }
     ~PcgWork()
     {
-        dfree(r); dfree(p); dfree(Ap); dfree(partial); dfree(hist); dfree(tmp); dfree(sc);
+        dfree(r); dfree(p); dfree(Ap); dfree(partial); dfree(partial2); dfree(hist); dfree(tmp); dfree(sc);
         if (h_hist) (void)hipHostFree(h_hist);
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -523,27 +525,31 @@ struct NoHook {
     int operator()(int) const { return PA_OK; }
 };
 
-// (P)CG iterations (Saad, Alg. 9.1) with Jacobi dinv (nullptr: none); after(it) runs once
-// iteration it has been enqueued.
+// (P)CG iterations (Saad, Alg. 9.1) with Jacobi dinv (nullptr: none) from the state cg_init
+// left in w; after(it) runs once iteration it has been enqueued.  apply(p, Ap) must add A p
+// into Ap, which holds zeros on entry (the direction update clears it for the next one).
 template <class T, class ApplyF, class AfterF = NoHook>
 int pcg_iterate(ApplyF apply, T *x, const T *dinv, int64_t n, double tol2, int max_it, int check, PcgWork<T> &w,
                 hipStream_t s, double rr0, int *iters, double *rr_out, AfterF after = AfterF())
 {
+    HIP_OK(vec_fill(w.Ap, T(0), n, s));
     auto step = [&](int it) -> int {
         int rc = apply(w.p, w.Ap);
         if (rc) return rc;
-        HIP_OK(cg_alpha<T>(w.p, w.Ap, n, w.partial, w.sc, s));
-        HIP_OK(cg_update<T>(x, w.r, w.p, w.Ap, dinv, n, w.partial, w.sc, w.hist, it, s));
+        HIP_OK(cg_pap<T>(w.p, w.Ap, n, w.partial2, s));
+        HIP_OK(cg_update_xr<T>(x, w.r, w.p, w.Ap, dinv, n, w.partial2, w.partial, w.sc, s));
+        HIP_OK(cg_update_dir<T>(w.p, w.r, dinv, w.Ap, n, w.partial, w.sc, w.hist, it, 1.0, s));
         return after(it);
     };
     return lagged_iterate<T>(step, tol2, max_it, check, w, s, rr0, iters, rr_out);
 }
 }  // namespace
 
-// y = A p with p vanishing on the essential DOFs (CG invariant): A_c p = A p outside, 0 on them.
-static int cg_apply(pa_op *op, bool constrained, const double *p, double *y, hipStream_t s)
+// y = A p with p vanishing on the essential DOFs (CG invariant): A_c p = A p outside, 0 on
+// them.  zero_first = false: y holds zeros on entry (pcg_iterate's contract).
+static int cg_apply(pa_op *op, bool constrained, const double *p, double *y, hipStream_t s, bool zero_first = true)
 {
-    int rc = do_apply(op, op->variant, p, y, s);
+    int rc = do_apply(op, op->variant, p, y, s, zero_first);
     if (rc) return rc;
     if (constrained && op->ness) HIP_OK(vec_zero_list(y, op->d_ess, op->ness, s));
     return PA_OK;
@@ -584,7 +590,7 @@ static int solve_mixed_ir(pa_op *op, const double *b, double *x, const pa_cg_opt
     }
     std::unique_ptr<void, void (*)(void *)> g2(dinv32, dfree);
     auto apply32 = [&](const float *p, float *y) -> int {
-        int r2 = do_apply_lp(op, p, y, fmt, s);
+        int r2 = do_apply_lp(op, p, y, fmt, s, false);
         if (r2) return r2;
         if (con && op->ness) HIP_OK(vec_set_list(y, 0.0f, op->d_ess, op->ness, s));
         return PA_OK;
@@ -705,7 +711,7 @@ static int solve_fcg(pa_op *op, const double *b, double *x, const pa_cg_opts *o,
         HIP_OK(hipMemcpyAsync(w.h_hist, w.hist, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
         int it2 = 0;
-        auto apply64 = [&](const double *p, double *y) { return cg_apply(op, con, p, y, s); };
+        auto apply64 = [&](const double *p, double *y) { return cg_apply(op, con, p, y, s, false); };
         status = pcg_iterate<double>(apply64, x, dinv, n, tol2, o->max_it - it, check, w, s, w.h_hist[0], &it2, &rr);
         if (status != PA_OK && status != PA_ERR_NOT_CONVERGED && status != PA_ERR_BREAKDOWN) return status;
         it += it2;
@@ -791,7 +797,7 @@ static int solve_mixed_ru(pa_op *op, const double *b, double *x, const pa_cg_opt
         HIP_OK(vec_to_f32(w32.r, w64.Ap, ns, n, s));
         HIP_OK(vec_fill(xh, 0.0f, n, s));
         HIP_OK(cg_rz_partials<float>(w32.r, dinv32, n, w32.partial, s));
-        HIP_OK(cg_update_dir<float>(w32.p, w32.r, dinv32, n, w32.partial, w32.sc, w32.hist, total, f, s));
+        HIP_OK(cg_update_dir<float>(w32.p, w32.r, dinv32, w32.Ap, n, w32.partial, w32.sc, w32.hist, total, f, s));
         scale = ns;
         first = false;
         // chunk length from the observed rate (iterations per factor of reduction)
@@ -802,13 +808,14 @@ static int solve_mixed_ru(pa_op *op, const double *b, double *x, const pa_cg_opt
         }
         k = std::min(k, max_total - total);
         for (int j = 1; j <= k; ++j) {
-            rc = do_apply_lp(op, w32.p, w32.Ap, fmt, s);
+            rc = do_apply_lp(op, w32.p, w32.Ap, fmt, s, false);
             if (rc) return rc;
             if (con && op->ness) HIP_OK(vec_set_list(w32.Ap, 0.0f, op->d_ess, op->ness, s));
-            HIP_OK(cg_alpha<float>(w32.p, w32.Ap, n, w32.partial, w32.sc, s));
-            HIP_OK(cg_update_xr<float>(xh, w32.r, w32.p, w32.Ap, dinv32, n, w32.partial, w32.sc, s));
+            HIP_OK(cg_pap<float>(w32.p, w32.Ap, n, w32.partial2, s));
+            HIP_OK(cg_update_xr<float>(xh, w32.r, w32.p, w32.Ap, dinv32, n, w32.partial2, w32.partial, w32.sc, s));
             if (j < k)
-                HIP_OK(cg_update_dir<float>(w32.p, w32.r, dinv32, n, w32.partial, w32.sc, w32.hist, total + j, 1.0, s));
+                HIP_OK(cg_update_dir<float>(w32.p, w32.r, dinv32, w32.Ap, n, w32.partial, w32.sc, w32.hist, total + j,
+                                            1.0, s));
         }
         total += k;
         HIP_OK(vec_axpy_f32(x, 1.0 / scale, xh, n, s));
@@ -865,7 +872,7 @@ static int solve_mixed_fcg(pa_op *op, const double *b, double *x, const pa_cg_op
     std::unique_ptr<void, void (*)(void *)> g5(tmp, dfree);
     HIP_OK(vec_to_f32(dinv32, dinv64, 1.0, n, s));
     auto apply32 = [&](const float *p, float *y) -> int {
-        int r2 = do_apply_lp(op, p, y, fmt, s);
+        int r2 = do_apply_lp(op, p, y, fmt, s, false);
         if (r2) return r2;
         if (con && op->ness) HIP_OK(vec_set_list(y, 0.0f, op->d_ess, op->ness, s));
         return PA_OK;
@@ -1004,7 +1011,7 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     auto t0 = std::chrono::steady_clock::now();
     int it = 0;
     double rr = 0.0;
-    auto apply64 = [&](const double *p, double *y) { return cg_apply(op, con, p, y, s); };
+    auto apply64 = [&](const double *p, double *y) { return cg_apply(op, con, p, y, s, false); };
     // iterates requested by the caller (training-data capture)
     int cap = 0;
     auto capture = [&](int k) -> int {

@@ -8,6 +8,7 @@ constexpr int kRedBlocks = 1024;  // fixed block count of every reduction: repro
 
 struct CgScalars {
     double rz, rr, pAp, alpha, beta;
+    double rz_prev;  // rz of the previous iteration (read by the direction update)
     int breakdown;
     int pad;
 };
@@ -26,27 +27,30 @@ hipError_t vec_dot(const T *x, const T *y, int64_t n, double *partial, double *o
 template <class T>
 hipError_t cg_init(const T *b, T *r, T *p, const T *dinv, int64_t n, double *partial, CgScalars *sc, double *hist,
                    hipStream_t s);
-// alpha = rz / (p . Ap)
+// alpha = rz / (p . Ap) into sc (for the FCG update)
 template <class T>
 hipError_t cg_alpha(const T *p, const T *Ap, int64_t n, double *partial, CgScalars *sc, hipStream_t s);
-// x += alpha p, r -= alpha Ap, beta, p = dinv r + beta p; hist[2 it] = r.r, hist[2 it + 1] = breakdown flag
-template <class T>
-hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
-                     double *hist, int it, hipStream_t s);
 
-// The two halves of cg_update, for solvers that act between them:
-// x += alpha p, r -= alpha Ap, partial sums of (r . dinv r, r . r)
+// One PCG iteration after y = A p is three kernels:
+//   cg_pap        partial sums of p . Ap                                   -> pap_part
+//   cg_update_xr  alpha = rz / (p . Ap) (breakdown if not > 0), x += alpha p, r -= alpha Ap,
+//                 rz_prev = rz, partial sums of (r . dinv r, r . r)         -> rz_part
+//   cg_update_dir beta = rz_new / (rz_prev f), rz = rz_new, p = dinv r + beta p, Ap = 0
+//                 (when Ap_zero is given: the next apply accumulates into it);
+//                 hist[2 it] = r.r, hist[2 it + 1] = breakdown flag
+// pap_part and rz_part are separate arrays of kRedBlocks (x2) doubles.  cg_rz_partials
+// writes rz_part for a given r (after a residual replacement); f is the factor by which r
+// and p were rescaled since rz_prev was taken (1 if they were not).
 template <class T>
-hipError_t cg_update_xr(T *x, T *r, const T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
-                        hipStream_t s);
-// the same partial sums for a given r (after it has been replaced)
+hipError_t cg_pap(const T *p, const T *Ap, int64_t n, double *pap_part, hipStream_t s);
 template <class T>
-hipError_t cg_rz_partials(const T *r, const T *dinv, int64_t n, double *partial, hipStream_t s);
-// beta = rz_new / (rz f), rz = rz_new, p = dinv r + beta p; hist as cg_update.  f: factor by
-// which r and p were rescaled since rz was taken (1 if they were not)
+hipError_t cg_update_xr(T *x, T *r, const T *p, const T *Ap, const T *dinv, int64_t n, const double *pap_part,
+                        double *rz_part, CgScalars *sc, hipStream_t s);
 template <class T>
-hipError_t cg_update_dir(T *p, const T *r, const T *dinv, int64_t n, double *partial, CgScalars *sc, double *hist,
-                         int it, double f, hipStream_t s);
+hipError_t cg_rz_partials(const T *r, const T *dinv, int64_t n, double *rz_part, hipStream_t s);
+template <class T>
+hipError_t cg_update_dir(T *p, const T *r, const T *dinv, T *Ap_zero, int64_t n, const double *rz_part, CgScalars *sc,
+                         double *hist, int it, double f, hipStream_t s);
 
 // ------------------------------------------------------------------ FCG vectors
 // x += alpha p; rold = r; r -= alpha Ap; hist[2 it] = r.r, hist[2 it + 1] = breakdown

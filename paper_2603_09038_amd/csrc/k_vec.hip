@@ -118,13 +118,28 @@ __global__ void k_cg_alpha(const double *partial, int nb, CgScalars *s)
     }
 }
 
-// x += alpha p; r -= alpha Ap; partial sums of (r . dinv r) and (r . r).
+// alpha = rz / (p . Ap) from the partial sums of p . Ap, formed identically (same order) in
+// every block; x += alpha p; r -= alpha Ap; rz_prev = rz; partial sums of (r . dinv r) and
+// (r . r) into rz_part.
 template <class T>
 __global__ void k_cg_update1(T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ Ap,
-                             const T *__restrict__ dinv, int64_t n, const CgScalars *__restrict__ s, double *partial)
+                             const T *__restrict__ dinv, int64_t n, CgScalars *__restrict__ s,
+                             const double *__restrict__ pap_part, int nb, double *__restrict__ rz_part)
 {
     __shared__ double sh[2 * 256];
-    const double alpha = s->alpha;
+    double a[1] = {0.0};
+    for (int i = threadIdx.x; i < nb; i += 256) a[0] += pap_part[i];
+    block_sum<1>(a, sh);
+    const double pAp = a[0], rz = s->rz;
+    const bool bad = !(pAp > 0.0) || !isfinite(pAp) || !isfinite(rz);
+    const double alpha = bad ? 0.0 : rz / pAp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->pAp = pAp;
+        s->alpha = alpha;
+        s->rz_prev = rz;
+        if (bad) s->breakdown = 1;
+    }
+    __syncthreads();  // sh is reused below
     double v[2] = {0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] = (T)fma(alpha, (double)p[i], (double)x[i]);
@@ -136,43 +151,42 @@ __global__ void k_cg_update1(T *__restrict__ x, T *__restrict__ r, const T *__re
     }
     block_sum<2>(v, sh);
     if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = v[0];
-        partial[2 * blockIdx.x + 1] = v[1];
+        rz_part[2 * blockIdx.x] = v[0];
+        rz_part[2 * blockIdx.x + 1] = v[1];
     }
 }
 
-// beta = rz_new / (rz f); rz = rz_new; record ||r||^2 for iteration `it`.  f != 1 when
-// the vectors were rescaled by f since rz was taken (rz scales by f^2, the old direction
-// p by f: folding one f into beta rescales p inside the direction update).
-__global__ void k_cg_beta(const double *partial, int nb, CgScalars *s, double *rr_hist, int it, double f)
+// beta = rz_new / (rz_prev f) from the partial sums of (r . dinv r, r . r), formed in every
+// block; p = dinv r + beta p; Ap = 0 for the next apply (if given).  Block 0 stores
+// rz = rz_new, rr, beta and hist[2 it] = r.r, hist[2 it + 1] = breakdown flag.  f != 1 when
+// r and p were rescaled by f since rz_prev was taken (rz scales by f^2, the old direction
+// by f: one f folded into beta rescales p inside the update).
+template <class T>
+__global__ void k_cg_update2(T *__restrict__ p, const T *__restrict__ r, const T *__restrict__ dinv,
+                             T *__restrict__ Ap_zero, int64_t n, CgScalars *__restrict__ s,
+                             const double *__restrict__ rz_part, int nb, double *__restrict__ rr_hist, int it, double f)
 {
     __shared__ double sh[2 * 256];
     double v[2] = {0.0, 0.0};
     for (int i = threadIdx.x; i < nb; i += 256) {
-        v[0] += partial[2 * i];
-        v[1] += partial[2 * i + 1];
+        v[0] += rz_part[2 * i];
+        v[1] += rz_part[2 * i + 1];
     }
     block_sum<2>(v, sh);
-    if (threadIdx.x == 0) {
-        const double rz_new = v[0];
+    const double rz_new = v[0], rzp = s->rz_prev;
+    const double beta = (rzp != 0.0) ? rz_new / (rzp * f) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (!isfinite(rz_new) || !isfinite(v[1])) s->breakdown = 1;
-        s->beta = (s->rz != 0.0) ? rz_new / (s->rz * f) : 0.0;
+        s->beta = beta;
         s->rz = rz_new;
         s->rr = v[1];
         rr_hist[2 * it] = v[1];
         rr_hist[2 * it + 1] = (double)s->breakdown;
     }
-}
-
-// p = dinv r + beta p
-template <class T>
-__global__ void k_cg_update2(T *__restrict__ p, const T *__restrict__ r, const T *__restrict__ dinv, int64_t n,
-                             const CgScalars *__restrict__ s)
-{
-    const double beta = s->beta;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double zi = dinv ? (double)(dinv[i] * r[i]) : (double)r[i];
         p[i] = (T)fma(beta, (double)p[i], zi);
+        if (Ap_zero) Ap_zero[i] = T(0);
     }
 }
 
@@ -397,47 +411,44 @@ hipError_t cg_alpha(const T *p, const T *Ap, int64_t n, double *partial, CgScala
     return hipGetLastError();
 }
 template <class T>
-hipError_t cg_update(T *x, T *r, T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
-                     double *hist, int it, hipStream_t s)
+hipError_t cg_pap(const T *p, const T *Ap, int64_t n, double *pap_part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_update1<T>, dim3(kRedBlocks), dim3(256), 0, s, x, r, p, Ap, dinv, n, sc, partial);
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc, hist, it, 1.0);
-    hipLaunchKernelGGL(k_cg_update2<T>, dim3(kRedBlocks), dim3(256), 0, s, p, r, dinv, n, sc);
+    hipLaunchKernelGGL(k_dot_partial<T>, dim3(kRedBlocks), dim3(256), 0, s, p, Ap, n, pap_part);
     return hipGetLastError();
 }
 template <class T>
-hipError_t cg_update_xr(T *x, T *r, const T *p, const T *Ap, const T *dinv, int64_t n, double *partial, CgScalars *sc,
-                        hipStream_t s)
+hipError_t cg_update_xr(T *x, T *r, const T *p, const T *Ap, const T *dinv, int64_t n, const double *pap_part,
+                        double *rz_part, CgScalars *sc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_update1<T>, dim3(kRedBlocks), dim3(256), 0, s, x, r, p, Ap, dinv, n, sc, partial);
+    hipLaunchKernelGGL(k_cg_update1<T>, dim3(kRedBlocks), dim3(256), 0, s, x, r, p, Ap, dinv, n, sc, pap_part,
+                       kRedBlocks, rz_part);
     return hipGetLastError();
 }
 template <class T>
-hipError_t cg_rz_partials(const T *r, const T *dinv, int64_t n, double *partial, hipStream_t s)
+hipError_t cg_rz_partials(const T *r, const T *dinv, int64_t n, double *rz_part, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cg_init<T>, dim3(kRedBlocks), dim3(256), 0, s, nullptr, const_cast<T *>(r), nullptr, dinv, n,
-                       partial);
+                       rz_part);
     return hipGetLastError();
 }
 template <class T>
-hipError_t cg_update_dir(T *p, const T *r, const T *dinv, int64_t n, double *partial, CgScalars *sc, double *hist,
-                         int it, double f, hipStream_t s)
+hipError_t cg_update_dir(T *p, const T *r, const T *dinv, T *Ap_zero, int64_t n, const double *rz_part, CgScalars *sc,
+                         double *hist, int it, double f, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, partial, kRedBlocks, sc, hist, it, f);
-    hipLaunchKernelGGL(k_cg_update2<T>, dim3(kRedBlocks), dim3(256), 0, s, p, r, dinv, n, sc);
+    hipLaunchKernelGGL(k_cg_update2<T>, dim3(kRedBlocks), dim3(256), 0, s, p, r, dinv, Ap_zero, n, sc, rz_part,
+                       kRedBlocks, hist, it, f);
     return hipGetLastError();
 }
 #define HEXPA_INST(T)                                                                                           \
     template hipError_t cg_init<T>(const T *, T *, T *, const T *, int64_t, double *, CgScalars *, double *,   \
                                    hipStream_t);                                                               \
     template hipError_t cg_alpha<T>(const T *, const T *, int64_t, double *, CgScalars *, hipStream_t);         \
-    template hipError_t cg_update<T>(T *, T *, T *, const T *, const T *, int64_t, double *, CgScalars *,      \
-                                     double *, int, hipStream_t);                                              \
-    template hipError_t cg_update_xr<T>(T *, T *, const T *, const T *, const T *, int64_t, double *,          \
-                                        CgScalars *, hipStream_t);                                             \
+    template hipError_t cg_pap<T>(const T *, const T *, int64_t, double *, hipStream_t);                      \
+    template hipError_t cg_update_xr<T>(T *, T *, const T *, const T *, const T *, int64_t, const double *,    \
+                                        double *, CgScalars *, hipStream_t);                                   \
     template hipError_t cg_rz_partials<T>(const T *, const T *, int64_t, double *, hipStream_t);              \
-    template hipError_t cg_update_dir<T>(T *, const T *, const T *, int64_t, double *, CgScalars *, double *,  \
-                                         int, double, hipStream_t);
+    template hipError_t cg_update_dir<T>(T *, const T *, const T *, T *, int64_t, const double *, CgScalars *, \
+                                         double *, int, double, hipStream_t);
 HEXPA_INST(double)
 HEXPA_INST(float)
 

@@ -245,3 +245,46 @@ def test_full_size_c2_sampled_rows(hx):
     one = torch.ones(op.ndof, dtype=torch.float64, device="cuda")
     assert float(op.apply(one).abs().max()) <= 1e-12 * scale
     op.close()
+
+
+# the order sweep at its full sizes (about 30 M DOFs each), default kernel choice
+@pytest.mark.parametrize("n,p", [(155, 2), (78, 4), (52, 6), (40, 8)])
+@pytest.mark.parametrize("ops", [1, 2])
+def test_full_size_sweep_sampled_rows(hx, n, p, ops):
+    import torch
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    op = hx.PAOperator(mesh, p, p + 2, ops=ops)
+    assert op.ndof == (n * p + 1) ** 3
+    x = synth.rand_x(op.ndof, 0)
+    y = op.apply(_cuda(x)).cpu().numpy()
+    rows = np.unique(np.concatenate([np.random.default_rng(p).integers(0, op.ndof, 48), [0, op.ndof - 1]]))
+    ref = oracle.Problem(mesh, p, p + 2, ops=_ops_o(ops)).apply_rows(x, rows)
+    scale = np.abs(ref).max()
+    assert np.abs(y[rows] - ref).max() <= TOL * 10 * scale, (n, p, ops)
+    # properties that hold at any size: K 1 = 0; 1^T M 1 = volume of the unit cube
+    one = torch.ones(op.ndof, dtype=torch.float64, device="cuda")
+    y1 = op.apply(one)
+    if ops == 2:
+        assert float(y1.abs().max()) <= 1e-12 * scale
+    else:
+        assert abs(float(y1.sum()) - 1.0) <= 1e-12
+    op.close()
+
+
+def test_full_size_mixed_workload_lp_apply_sampled_rows(hx):
+    """32^3, p=6, Q=8, log-normal coefficient (7,189,057 DOFs): the 16-bit apply on sampled
+    rows against the oracle, max-norm over the rows within 16u of the rows' scale."""
+    import torch
+    n, p, q = 32, 6, 8
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    grid, _ = synth.lognormal_kappa_grid(0, sigma=1.0, ell=0.1)
+    op = hx.PAOperator(mesh, p, q, coeff={"kind": hx.PA_COEFF_GRID, "grid": grid}, ops=2)
+    x = synth.rand_x(op.ndof, 0)
+    rows = np.unique(np.concatenate([np.random.default_rng(6).integers(0, op.ndof, 48), [0, op.ndof - 1]]))
+    ref = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.from_grid(grid), ops=oracle.DIFFUSION).apply_rows(x, rows)
+    scale = np.abs(ref).max()
+    x32 = torch.tensor(x, dtype=torch.float32, device="cuda")
+    for fmt, u in ((hx.PA_LP_FP16, 2.0 ** -11), (hx.PA_LP_BF16, 2.0 ** -8)):
+        y = op.apply_lp(x32, fmt=fmt).double().cpu().numpy()
+        assert np.abs(y[rows] - ref).max() <= 16 * u * scale, (fmt, np.abs(y[rows] - ref).max() / scale)
+    op.close()
