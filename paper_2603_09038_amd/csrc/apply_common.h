@@ -62,8 +62,11 @@ constexpr int cmax3(int a, int b, int c) { return cmax(a, cmax(b, c)); }
 constexpr int cclamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // ------------------------------------------------------------------ element-group shape
-template <int D, int Q, int OPS, int TB = 8>  // TB: bytes of the LDS/vector scalar type
+// TB: bytes of the LDS/vector scalar type; NT: threads per workgroup; BUDGET: LDS bytes per
+// workgroup for the element tensors
+template <int D, int Q, int OPS, int TB = 8, int NT = kThreads, int BUDGET = kLdsBudget>
 struct Shape {
+    static constexpr int THREADS = NT;
     static constexpr bool kMass = (OPS & 1) != 0;
     static constexpr bool kDiff = (OPS & 2) != 0;
     static constexpr int NCOMP = kDiff ? (kMass ? 7 : 6) : 1;  // stored D values per qp
@@ -81,8 +84,8 @@ struct Shape {
     static constexpr int SLACK = 16 * 2 * kMaxQ;  // tail of each buffer for padded tile columns
     static constexpr int PER_ELEM_BYTES = TB * (SZ_A + SZ_B) + 4 * D3;
     // elements per workgroup from the LDS budget (48 KB -> 3 workgroups per 160 KB CU)
-    static constexpr int E = cclamp(kLdsBudget / PER_ELEM_BYTES, 1, 32);
-    static constexpr int NS = (E * Q3 + kThreads - 1) / kThreads;  // qp slots per thread
+    static constexpr int E = cclamp(BUDGET / PER_ELEM_BYTES, 1, 32);
+    static constexpr int NS = (E * Q3 + NT - 1) / NT;  // qp slots per thread
 };
 
 // ------------------------------------------------------------------ table accessors
@@ -156,14 +159,14 @@ struct Tiling {
     static constexpr int TPE = NCOLP / 16;
 };
 
-template <class P, int E, class Out>
+template <class P, int E, int NT, class Out>
 __device__ __forceinline__ void mfma_pass(const double *in, int szin,
                                           const double (&a)[PassRegs<P>::RT][PassRegs<P>::KC],
                                           const Out &out, int wave, int lane)
 {
     constexpr int C = P::C, K = PassRegs<P>::K, KC = PassRegs<P>::KC, RT = PassRegs<P>::RT;
-    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE;
-    constexpr int NR = (NTILE + kWaves - 1) / kWaves;
+    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE, NW = NT / 64;
+    constexpr int NR = (NTILE + NW - 1) / NW;
     constexpr int BATCH = NR < kMfmaBatch ? NR : kMfmaBatch;
     const int kl = lane >> 4, nl = lane & 15;
     // lane constants: B-operand offsets per k chunk, output offset of row kl
@@ -184,7 +187,7 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
         bool cv[BATCH];
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
-            const int t = wave + kWaves * (r0 + bi);  // wave-uniform
+            const int t = wave + NW * (r0 + bi);  // wave-uniform
             const bool tv = (r0 + bi < NR) && t < NTILE;
             const int e = tv ? t / TPE : 0;
             const int n0 = tv ? (t - e * TPE) * 16 : 0;
@@ -225,24 +228,24 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
 // over a wave; consecutive threads take consecutive columns, so LDS reads stay
 // conflict-free); each thread keeps its outputs in registers.  BATCH work items per
 // thread are loaded before any FMA so the LDS latency of one hides behind another.
-template <class P, int E>
+template <class P, int E, int NT>
 struct ValuShape {
     static constexpr int NCOLS = E * P::NCOL;
     static constexpr int NCOLP = ((NCOLS + 63) / 64) * 64;  // whole waves per output part
-    static constexpr int S = (kValuSplit >= 4 && 4 * NCOLP <= kThreads && P::O >= 8)   ? 4
-                             : (kValuSplit >= 2 && 2 * NCOLP <= kThreads && P::O >= 4) ? 2
+    static constexpr int S = (kValuSplit >= 4 && 4 * NCOLP <= NT && P::O >= 8)   ? 4
+                             : (kValuSplit >= 2 && 2 * NCOLP <= NT && P::O >= 4) ? 2
                                                                                         : 1;
     static constexpr int OP = (P::O + S - 1) / S;  // outputs per thread
     static constexpr int NTOT = S == 1 ? NCOLS : NCOLP * S;
 };
 
-template <class P, int E, class Out>
+template <class P, int E, int NTH, class Out>
 __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevTables *tab, const Out &out, int tid)
 {
     constexpr int C = P::C, NT = P::NT, O = P::O;
-    using V = ValuShape<P, E>;
+    using V = ValuShape<P, E, NTH>;
     constexpr int NTOT = V::NTOT, OP = V::OP;
-    constexpr int NR = (NTOT + kThreads - 1) / kThreads;
+    constexpr int NR = (NTOT + NTH - 1) / NTH;
     constexpr int BATCH = NR < kValuBatch ? NR : kValuBatch;
 #pragma unroll 1
     for (int r0 = 0; r0 < NR; r0 += BATCH) {
@@ -251,7 +254,7 @@ __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevT
         bool cv[BATCH];
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
-            const int it = tid + kThreads * (r0 + bi);
+            const int it = tid + NTH * (r0 + bi);
             int col = it, part = 0;
             if constexpr (V::S > 1) {
                 part = __builtin_amdgcn_readfirstlane(it / V::NCOLP);
@@ -360,15 +363,15 @@ __device__ __forceinline__ void load_a16(const DevTables *tab,
         }
 }
 
-template <class P, int E, bool BF, class Out>
+template <class P, int E, int NT, bool BF, class Out>
 __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
                                             const typename Mfma16<BF>::V (&a)[PassRegs16<P>::RB][PassRegs16<P>::KC],
                                             const Out &out, int wave, int lane)
 {
     using V = typename Mfma16<BF>::V;
     constexpr int C = P::C, K = PassRegs16<P>::K, KC = PassRegs16<P>::KC, RB = PassRegs16<P>::RB;
-    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE;
-    constexpr int NR = (NTILE + kWaves - 1) / kWaves;
+    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE, NW = NT / 64;
+    constexpr int NR = (NTILE + NW - 1) / NW;
     constexpr int BATCH = NR < kMfmaBatch ? NR : kMfmaBatch;
     const int kl = lane >> 4, nl = lane & 15;
     int lin[KC][4];
@@ -390,7 +393,7 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
         bool cv[BATCH];
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
-            const int t = wave + kWaves * (r0 + bi);
+            const int t = wave + NW * (r0 + bi);
             const bool tv = (r0 + bi < NR) && t < NTILE;
             const int e = tv ? t / TPE : 0;
             const int n0 = tv ? (t - e * TPE) * 16 : 0;

@@ -59,10 +59,23 @@ struct ExT {
 
 template <class S>
 struct GroupRegs {
-    static constexpr int NM = (S::E * S::D3 + kThreads - 1) / kThreads;  // map/x slots per thread
+    static constexpr int NM = (S::E * S::D3 + S::THREADS - 1) / S::THREADS;  // map/x slots per thread
 };
 
-// D of one group into registers: slot s of thread tid is qp entry L = tid + s*kThreads.
+// Workgroup size and LDS budget of the register-staged kernel: diffusion at p <= 4 runs
+// two-wave workgroups of two elements (fewer waves wait at each barrier, more workgroups
+// per CU); everything else four waves and a 48 KB budget (measured per order).
+#ifndef HEXPA_SMALL_WG_MAX_D
+#define HEXPA_SMALL_WG_MAX_D 5
+#endif
+template <int D, int OPS, int EX>
+struct ApplyCfg {
+    static constexpr bool SMALL = (OPS & 2) != 0 && D <= HEXPA_SMALL_WG_MAX_D && (EX == 0 || EX == 1);
+    static constexpr int NT = SMALL ? 128 : kThreads;
+    static constexpr int BUDGET = SMALL ? 20 * 1024 : kLdsBudget;
+};
+
+// D of one group into registers: slot s of thread tid is qp entry L = tid + s*THREADS.
 // EL: the launch passes an element list (only the coloured launches do).  Making it a
 // compile-time property keeps the list loads, and the memory waits their results need,
 // out of every other instance.
@@ -72,7 +85,7 @@ __device__ __forceinline__ void load_qdata(T (&dq)[S::NS][S::NCOMP], const T *__
 {
 #pragma unroll
     for (int s = 0; s < S::NS; ++s) {
-        const int L = tid + s * kThreads;
+        const int L = tid + s * S::THREADS;
         const int e = L / S::Q3, r = L - e * S::Q3;
         const bool ok = e < nv;
         const int64_t ge = ok ? (EL ? elist[e0 + e] : e0 + e) : 0;
@@ -88,7 +101,7 @@ __device__ __forceinline__ void load_map(int32_t (&m)[GroupRegs<S>::NM], const i
 {
 #pragma unroll
     for (int s = 0; s < GroupRegs<S>::NM; ++s) {
-        const int L = tid + s * kThreads;
+        const int L = tid + s * S::THREADS;
         const int e = L / S::D3, I = L - e * S::D3;
         int32_t gi = -1;
         if (e < nv) {
@@ -110,7 +123,7 @@ __device__ __forceinline__ void load_x(T (&xv)[GroupRegs<S>::NM], const int32_t 
 // One contraction pass with the chosen executor.  MFMA A-operands are read from the LDS
 // copy of the tables right before the pass (short live ranges, no hoisting across the
 // barriers); the VALU executor reads the tables with uniform loads from global memory.
-template <class P, int E, int EX, class T, class Out>
+template <class P, int E, int EX, int NT, class T, class Out>
 __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables *stab, const DevTables *gtab,
                                          const Out &out, int tid)
 {
@@ -118,25 +131,27 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
     if constexpr (EX == EX_MFMA64) {
         double a[PassRegs<P>::RT][PassRegs<P>::KC];
         load_a<P>(stab, a, lane);
-        mfma_pass<P, E>(in, szin, a, out, wave, lane);
+        mfma_pass<P, E, NT>(in, szin, a, out, wave, lane);
     } else if constexpr (EX == EX_VALU64) {
-        valu_pass<P, E>(in, szin, gtab, out, tid);
+        valu_pass<P, E, NT>(in, szin, gtab, out, tid);
     } else {
         constexpr bool BF = EX == EX_MFMA16B;
         typename Mfma16<BF>::V a[PassRegs16<P>::RB][PassRegs16<P>::KC];
         load_a16<P, BF>(stab, a, lane);
-        mfma16_pass<P, E, BF>(in, szin, a, out, wave, lane);
+        mfma16_pass<P, E, NT, BF>(in, szin, a, out, wave, lane);
     }
 }
 
 template <int D, int Q, int OPS, int EX, bool ATOMIC>
-__global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
+__global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_apply(
     int nelem, int ngroups, const int32_t *__restrict__ elist, const int32_t *__restrict__ emap,
     const typename ExT<EX>::T *__restrict__ qd, const DevTables *__restrict__ tab,
     const typename ExT<EX>::T *__restrict__ x, typename ExT<EX>::T *__restrict__ y)
 {
     using T = typename ExT<EX>::T;
-    using S = Shape<D, Q, OPS, (int)sizeof(T)>;
+    using CFG = ApplyCfg<D, OPS, EX>;
+    using S = Shape<D, Q, OPS, (int)sizeof(T), CFG::NT, CFG::BUDGET>;
+    constexpr int NT = S::THREADS;
     constexpr int E = S::E, D3 = S::D3, Q3 = S::Q3, NS = S::NS, NC = S::NCOMP, NM = GroupRegs<S>::NM;
     constexpr bool M = S::kMass;
     constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
@@ -146,7 +161,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
     __shared__ DevTables stab;  // 1-D tables in LDS: MFMA A-operands are re-read per pass
 
     const int tid = threadIdx.x;
-    for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += kThreads)
+    for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
         reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
 
     // Workgroup b runs on XCD b % 8.  XCD x owns the contiguous group range
@@ -186,7 +201,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
         // stage x_E = G_e x (local node order = X[e][n=(j,k)][i]) and the map
 #pragma unroll
         for (int s = 0; s < NM; ++s) {
-            const int L = tid + s * kThreads;
+            const int L = tid + s * NT;
             if (L < E * D3) {
                 const int e = L / D3, I = L - e * D3;
                 lmap[L] = mcur[s];
@@ -201,20 +216,20 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
 
         // forward contractions
         if constexpr (S::kDiff) {
-            run_pass<DF1<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<DF2a<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DF2b<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             lds_barrier();
-            run_pass<DF3a<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DF3b<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DF3c<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3c<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
         } else {
-            run_pass<MF1<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MF1<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<MF2<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MF2<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             lds_barrier();
-            run_pass<MF3<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MF3<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
         }
         // the next group's map has had the forward passes to arrive: start its x gather
         T xnext[NM];
@@ -225,7 +240,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
         if constexpr (kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const int L = tid + s * kThreads;
+            const int L = tid + s * NT;
             if (L < E * Q3) {
                 const int e = L / Q3, r = L - e * Q3;
                 T *V = bufB + e * S::SZ_B + r;
@@ -257,23 +272,23 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply(
         // transposed contractions and scatter-add
         if constexpr (S::kDiff) {
             using CH = Chan<Q, M>;
-            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             if constexpr (M)
-                run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
+                run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
                                                                 tid);
             lds_barrier();
-            run_pass<DT2a<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DT2b<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DT2a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DT2b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<DT3<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
+            run_pass<DT3<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
         } else {
-            run_pass<MT1<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MT1<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             lds_barrier();
-            run_pass<MT2<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MT2<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<MT3<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
+            run_pass<MT3<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
         }
         if (!more) break;
         lds_barrier();  // LDS (X, map) is rewritten by the next group
@@ -355,9 +370,10 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
 {
     using T = typename ExT<EX>::T;
     using S = Shape<D, Q, OPS, (int)sizeof(T)>;
+    constexpr int NT = kThreads;
     constexpr int E = DmaShape<D, Q, OPS, T>::E, D3 = S::D3, Q3 = S::Q3, NC = S::NCOMP, ED3 = E * D3;
     constexpr bool DREG = DmaShape<D, Q, OPS, T>::DREG;
-    constexpr int NSD = (E * Q3 + kThreads - 1) / kThreads;
+    constexpr int NSD = (E * Q3 + NT - 1) / NT;
     constexpr int TPC = 16 / (int)sizeof(T), CPE = NC * Q3 / TPC, ECH = E * CPE;
     constexpr bool M = S::kMass, WIDE = sizeof(T) == 8;
     constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
@@ -371,7 +387,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += kThreads)
+    for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
         reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
 
     const int nb = gridDim.x;
@@ -391,7 +407,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
     // map of group gg into buffer b (absent element slots get -1)
     auto issue_map = [&](int gg, int b) {
         const int e0 = gg * E, nv = min(E, nelem - e0);
-        for (int L0 = wave * 64; L0 < ED3; L0 += kThreads) {
+        for (int L0 = wave * 64; L0 < ED3; L0 += NT) {
             const int L = L0 + lane;
             const uint32_t base = lds_byte_addr(&mapb[b][L0]);
             if (L < nv * D3) {
@@ -405,7 +421,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
     };
     // x gathered through the map in buffer b (absent slots read x[0], never scattered)
     auto issue_x = [&](int b) {
-        for (int L0 = wave * 64; L0 < ED3; L0 += kThreads) {
+        for (int L0 = wave * 64; L0 < ED3; L0 += NT) {
             const int L = L0 + lane;
             const uint32_t bl = lds_byte_addr(&XL[L0]);
             const uint32_t bh = WIDE ? lds_byte_addr(&XH[L0]) : 0u;
@@ -419,10 +435,10 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
     };
     auto issue_d = [&](int gg) {
         const int e0 = gg * E, nv = min(E, nelem - e0), nch = nv * CPE;
-        if constexpr (DREG) {  // into registers: slot s of thread tid is qp entry tid + s kThreads
+        if constexpr (DREG) {  // into registers: slot s of thread tid is qp entry tid + s NT
 #pragma unroll
             for (int s = 0; s < NSD; ++s) {
-                const int L = tid + s * kThreads;
+                const int L = tid + s * NT;
                 const int e = L / Q3, r = L - e * Q3;
                 const bool ok = e < nv;
                 const int64_t ge = ok ? (EL ? elist[e0 + e] : e0 + e) : 0;
@@ -432,7 +448,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
             }
             return;
         }
-        for (int c0 = wave * 64; c0 < ECH; c0 += kThreads) {
+        for (int c0 = wave * 64; c0 < ECH; c0 += NT) {
             const int ch = c0 + lane;
             const uint32_t base = lds_byte_addr(sD + c0 * TPC);
             if (ch < nch) {
@@ -460,7 +476,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
         const int mb1 = mb == 2 ? 0 : mb + 1, mb2 = mb1 == 2 ? 0 : mb1 + 1;
 
         // stage x_E from the gathered halves
-        for (int L = tid; L < ED3; L += kThreads) {
+        for (int L = tid; L < ED3; L += NT) {
             const int e = L / D3, I = L - e * D3;
             T v;
             if constexpr (WIDE) v = __hiloint2double((int)XH[L], (int)XL[L]);
@@ -473,20 +489,20 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
 
         // forward contractions
         if constexpr (S::kDiff) {
-            run_pass<DF1<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<DF2a<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DF2b<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             lds_barrier();
-            run_pass<DF3a<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DF3b<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DF3c<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3c<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
         } else {
-            run_pass<MF1<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MF1<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<MF2<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MF2<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             lds_barrier();
-            run_pass<MF3<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MF3<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
         }
         // D of this group, the next group's x and the map after it have landed
         dma_wait();
@@ -494,7 +510,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
 
 #pragma unroll
         for (int s = 0; s < NSD; ++s) {
-            const int L = tid + s * kThreads;
+            const int L = tid + s * NT;
             if (L < E * Q3) {
                 const int e = L / Q3, r = L - e * Q3;
                 T *V = bufB + e * S::SZ_B + r;
@@ -520,23 +536,23 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
         const int32_t *lmap = mapb[mb];
         if constexpr (S::kDiff) {
             using CH = Chan<Q, M>;
-            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             if constexpr (M)
-                run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
+                run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
                                                                 tid);
             lds_barrier();
-            run_pass<DT2a<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DT2b<D, Q, M>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DT2a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DT2b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<DT3<D, Q, M>, E, EX>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
+            run_pass<DT3<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
         } else {
-            run_pass<MT1<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MT1<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
             lds_barrier();
-            run_pass<MT2<D, Q>, E, EX>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MT2<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<MT3<D, Q>, E, EX>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
+            run_pass<MT3<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
         }
         if (!more) break;
         lds_barrier();  // bufA, XL/XH and the oldest map buffer are rewritten next
@@ -552,8 +568,11 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
                            typename ExT<EX>::T *y, const int32_t *elist, int n, hipStream_t s)
 {
     using T = typename ExT<EX>::T;
+    using CFG = ApplyCfg<D, OPS, EX>;
     constexpr bool DMA = DmaShape<D, Q, OPS, T>::ok;
-    constexpr int EG = DMA ? DmaShape<D, Q, OPS, T>::E : Shape<D, Q, OPS, (int)sizeof(T)>::E;
+    // elements per group and workgroup size exactly as the chosen kernel computes them
+    constexpr int EG = DMA ? DmaShape<D, Q, OPS, T>::E : Shape<D, Q, OPS, (int)sizeof(T), CFG::NT, CFG::BUDGET>::E;
+    constexpr int NT = DMA ? kThreads : CFG::NT;
     const int ngroups = (n + EG - 1) / EG;
     if (ngroups == 0) return hipSuccess;
     void (*kern)(int, int, const int32_t *, const int32_t *, const T *, const DevTables *, const T *, T *);
@@ -565,7 +584,7 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
         static int cap = 0;
         if (cap == 0) {
             int per_cu = 0, dev = 0, ncu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0) != hipSuccess || per_cu < 1)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess || per_cu < 1)
                 per_cu = 1;
             if (hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
@@ -574,7 +593,7 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
         }
         nblocks = ngroups < cap ? ngroups : cap;
     }
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kThreads), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab,
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab,
                        x, y);
     return hipGetLastError();
 }
