@@ -155,6 +155,12 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     constexpr int E = S::E, D3 = S::D3, Q3 = S::Q3, NS = S::NS, NC = S::NCOMP, NM = GroupRegs<S>::NM;
     constexpr bool M = S::kMass;
     constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
+    // two-wave workgroups: the independent y-direction passes (forward: on B x and on G x;
+    // transposed: the two paths) each get a wave of their own instead of sharing wave 0
+#ifndef HEXPA_PASS_PAIRS
+#define HEXPA_PASS_PAIRS 1
+#endif
+    constexpr bool PAIRS = HEXPA_PASS_PAIRS && NT == 128 && S::kDiff;
     __shared__ T bufA[E * S::SZ_A + S::SLACK];
     __shared__ T bufB[E * S::SZ_B + S::SLACK];
     __shared__ int32_t lmap[E * D3];
@@ -218,8 +224,15 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         if constexpr (S::kDiff) {
             run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
-            run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            if constexpr (PAIRS) {  // the two independent y passes on one wave each
+                if (tid < 64)
+                    run_pass<DF2a<D, Q, M>, E, EX, 64>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+                else
+                    run_pass<DF2b<D, Q, M>, E, EX, 64>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid - 64);
+            } else {
+                run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+                run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            }
             lds_barrier();
             run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
@@ -279,8 +292,15 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
                 run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
                                                                 tid);
             lds_barrier();
-            run_pass<DT2a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DT2b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            if constexpr (PAIRS) {
+                if (tid < 64)
+                    run_pass<DT2a<D, Q, M>, E, EX, 64>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+                else
+                    run_pass<DT2b<D, Q, M>, E, EX, 64>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid - 64);
+            } else {
+                run_pass<DT2a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+                run_pass<DT2b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            }
             lds_barrier();
             run_pass<DT3<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, GlobalOut<ATOMIC, T>{y, lmap, D3}, tid);
         } else {
