@@ -564,23 +564,32 @@ struct Pad {
 };
 
 template <int N>
-__global__ __launch_bounds__(64) void k_net16(int64_t nelem, const double *__restrict__ r,
-                                              const int32_t *__restrict__ emap, const float *__restrict__ logk,
-                                              const h4_t *__restrict__ wp, const float *__restrict__ prm,
-                                              const double *__restrict__ inv_mult, double scale,
-                                              double *__restrict__ z)
+__global__ __launch_bounds__(256, 3) void k_net16(int64_t nelem, const double *__restrict__ r,
+                                                  const int32_t *__restrict__ emap, const float *__restrict__ logk,
+                                                  const h4_t *__restrict__ wp, const float *__restrict__ prm,
+                                                  const double *__restrict__ inv_mult, double scale,
+                                                  double *__restrict__ z)
 {
+    // One element per workgroup of four waves: wave w owns GEMM row tiles w, w + 4, ...
+    // (16 tile points each), so each wave keeps few operands in flight and several
+    // workgroups share a CU.  Every tile point belongs to one thread in the gather,
+    // normalisation, layer-3 tap sum and scatter (P <= 256).  The layer-3 table is stored
+    // tap-major with an odd row pitch (in 4-byte words), so the 27 shifted reads of a wave
+    // hit distinct LDS banks.
     using T = Pad<N>;
-    constexpr int P = T::P, NP3 = T::NP3, RT = T::RT, NPL = (P + 63) / 64;
-    static_assert(RT * 16 * 32 <= NP3 * 16, "layer-3 table fits in the a1 buffer");
+    constexpr int P = T::P, NP3 = T::NP3, RT = T::RT;
+    constexpr int YP = 16 * RT + 2;  // row pitch of the layer-3 table (halves; odd in words)
+    static_assert(P <= 256, "one tile point per thread");
     __shared__ h4_t x0b[NP3];      // [point] (r/s, log kappa, 0, 0)
     __shared__ h4_t a1b[NP3 * 4];  // [point][channel group of 4]
     __shared__ h4_t a2b[NP3 * 4];
+    __shared__ _Float16 yb[32 * YP];  // layer-3 table [tap][row]
+    __shared__ double red[4];
     _Float16 *a1h = reinterpret_cast<_Float16 *>(a1b), *a2h = reinterpret_cast<_Float16 *>(a2b);
-    _Float16 *yb = a1h;  // layer-3 table [row < 16 RT][32 taps] reuses a1's space
-    const int l = threadIdx.x, g = l >> 4, col = l & 15;
+    const int tid = threadIdx.x, l = tid & 63, g = l >> 4, col = l & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const h4_t zero4 = {0, 0, 0, 0};
-    for (int i = l; i < NP3; i += 64) {
+    for (int i = tid; i < NP3; i += 256) {
         x0b[i] = zero4;
 #pragma unroll
         for (int k = 0; k < 4; ++k) a1b[i * 4 + k] = a2b[i * 4 + k] = zero4;
@@ -593,130 +602,132 @@ __global__ __launch_bounds__(64) void k_net16(int64_t nelem, const double *__res
 #pragma unroll
     for (int s = 0; s < kPackL3; ++s) w3[s] = wp[(kPackL1 + kPackL2 + s) * 64 + l];
     const float bias1 = prm[kNetOffB1 + col], bias2 = prm[kNetOffB2 + col], bias3 = prm[kNetOffB3];
-    int rb[RT];  // padded index of this lane's GEMM row in every row tile (dummy rows repeat the last point)
+    constexpr int MT = (RT + 3) / 4;  // row tiles per wave (the last ones may be absent)
+    // A wave's tiles past RT (only when RT is not a multiple of 4) compute on clamped rows
+    // and store nothing: the MFMA loops carry no per-tile branches.
+    int rb[MT];                        // padded index of this lane's A-operand row (dummy rows repeat the last point)
+    int op[MT][4];                     // padded index of each result row this lane holds, -1 past the tile
+    bool tv[MT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) rb[rt] = T::pad(min(16 * rt + col, P - 1));
-    // layer-1 tap offset of this lane's k-group in every k-step (taps past 26 carry zero weights)
-    int o1[kPackL1];
+    for (int m = 0; m < MT; ++m) {
+        const int rt = wave + 4 * m;
+        tv[m] = rt < RT;
+        rb[m] = T::pad(min(16 * rt + col, P - 1));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p = 16 * rt + 4 * g + v;
+            op[m][v] = (tv[m] && p < P) ? T::pad(p) : -1;
+        }
+    }
+    int o1[kPackL1];  // layer-1 tap offset of this lane's k-group in every k-step (taps past 26: zero weights)
 #pragma unroll
     for (int s = 0; s < kPackL1; ++s) o1[s] = 4 * s + g < 27 ? T::off(4 * s + g) : 0;
+    const bool own = tid < P;  // this thread's tile point
+    const int pp = own ? T::pad(tid) : 0;
+    uint32_t inmask = 0;  // bit tap: the neighbour (tap) of this thread's point lies in the tile
+    {
+        const int pi = tid % N, pj = (tid / N) % N, pk = tid / (N * N);
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+            if ((unsigned)(pi + dx) < (unsigned)N && (unsigned)(pj + dy) < (unsigned)N && (unsigned)(pk + dz) < (unsigned)N)
+                inmask |= 1u << tap;
+        }
+    }
     __syncthreads();
 
     for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
         // gather r, element RMS
-        double rv[NPL];
-        int32_t gi[NPL];
-        double ss = 0.0;
-#pragma unroll
-        for (int k = 0; k < NPL; ++k) {
-            const int p = l + 64 * k;
-            rv[k] = 0.0;
-            gi[k] = 0;
-            if (p < P) {
-                gi[k] = emap[e * P + p];
-                rv[k] = r[gi[k]];
-                ss = fma(rv[k], rv[k], ss);
-            }
+        int32_t gi = 0;
+        double rv = 0.0;
+        float lk = 0.f;
+        if (own) {
+            gi = emap[e * P + tid];
+            rv = r[gi];
+            lk = logk[e * P + tid];
         }
+        double ss = rv * rv;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m);
+        if (l == 0) red[wave] = ss;
+        __syncthreads();
+        ss = (red[0] + red[1]) + (red[2] + red[3]);
         const double rms = sqrt(ss / P);
         const double sc = rms > 0.0 ? rms : 1.0;
-        float lk[NPL];
-#pragma unroll
-        for (int k = 0; k < NPL; ++k) lk[k] = (l + 64 * k < P) ? logk[e * P + l + 64 * k] : 0.f;
 
         // the network on +r and on -r; the preconditioner takes the odd part
-        float odd[NPL];
-#pragma unroll
-        for (int k = 0; k < NPL; ++k) odd[k] = 0.f;
+        float odd = 0.f;
 #pragma unroll 1
         for (int sgn = 0; sgn < 2; ++sgn) {
-            const double sg = sgn ? -1.0 : 1.0;
-#pragma unroll
-            for (int k = 0; k < NPL; ++k) {
-                const int p = l + 64 * k;
-                if (p < P) {
-                    h4_t v = {(_Float16)(float)(sg * rv[k] / sc), (_Float16)lk[k], (_Float16)0.f, (_Float16)0.f};
-                    x0b[T::pad(p)] = v;
-                }
+            if (own) {
+                const h4_t v = {(_Float16)(float)((sgn ? -rv : rv) / sc), (_Float16)lk, (_Float16)0.f, (_Float16)0.f};
+                x0b[pp] = v;
             }
             __syncthreads();
-
-            f4_t acc[RT];
+            f4_t acc[MT];
             // layer 1: 2 (padded to 4) -> 16 channels, ReLU
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt] = (f4_t){0.f, 0.f, 0.f, 0.f};
+            for (int m = 0; m < MT; ++m) acc[m] = (f4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < kPackL1; ++s)
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16f16(x0b[rb[rt] + o1[s]], w1[s], acc[rt], 0, 0, 0);
+                for (int m = 0; m < MT; ++m)
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(x0b[rb[m] + o1[s]], w1[s], acc[m], 0, 0, 0);
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
+            for (int m = 0; m < MT; ++m)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int p = 16 * rt + 4 * g + v;
-                    if (p < P) a1h[T::pad(p) * 16 + col] = (_Float16)fmaxf(acc[rt][v] + bias1, 0.f);
-                }
+                for (int v = 0; v < 4; ++v)
+                    if (op[m][v] >= 0) a1h[op[m][v] * 16 + col] = (_Float16)fmaxf(acc[m][v] + bias1, 0.f);
             __syncthreads();
-            // layer 2: 16 -> 16, one tap per k-step, ReLU
+            // layer 2: 16 -> 16, one tap per k-step, ReLU; the taps in three chunks of nine so
+            // that the compiler keeps at most a chunk's operand loads in flight (registers)
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) acc[rt] = (f4_t){0.f, 0.f, 0.f, 0.f};
+            for (int m = 0; m < MT; ++m) acc[m] = (f4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < 27; ++s)
+            for (int s0 = 0; s0 < 27; s0 += 9) {
+                asm volatile("" ::: "memory");
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt)
-                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1b[(rb[rt] + T::off(s)) * 4 + g], w2[s], acc[rt],
-                                                                    0, 0, 0);
+                for (int s = s0; s < s0 + 9; ++s)
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
+                    for (int m = 0; m < MT; ++m)
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1b[(rb[m] + T::off(s)) * 4 + g], w2[s],
+                                                                       acc[m], 0, 0, 0);
+            }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int p = 16 * rt + 4 * g + v;
-                    if (p < P) a2h[T::pad(p) * 16 + col] = (_Float16)fmaxf(acc[rt][v] + bias2, 0.f);
-                }
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (op[m][v] >= 0) a2h[op[m][v] * 16 + col] = (_Float16)fmaxf(acc[m][v] + bias2, 0.f);
             __syncthreads();
-            // layer 3, part 1: Y[pt][tap] for every tile point and tap
+            // layer 3, part 1: Y[pt][tap] for every tile point and tap (rows past the tile unused)
 #pragma unroll
             for (int ct = 0; ct < kPackL3; ++ct)
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    const f4_t y = __builtin_amdgcn_mfma_f32_16x16x16f16(a2b[rb[rt] * 4 + g], w3[ct],
+                for (int m = 0; m < MT; ++m) {
+                    const f4_t y = __builtin_amdgcn_mfma_f32_16x16x16f16(a2b[rb[m] * 4 + g], w3[ct],
                                                                          (f4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    if (tv[m])
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) yb[(16 * rt + 4 * g + v) * 32 + 16 * ct + col] = (_Float16)y[v];
+                        for (int v = 0; v < 4; ++v)
+                            yb[(16 * ct + col) * YP + 16 * (wave + 4 * m) + 4 * g + v] = (_Float16)y[v];
                 }
             __syncthreads();
             // layer 3, part 2: shifted sum over taps (the bias cancels in the odd part)
+            if (own) {
+                float o = bias3;
 #pragma unroll
-            for (int k = 0; k < NPL; ++k) {
-                const int p = l + 64 * k;
-                if (p < P) {
-                    float mk[27];
-                    tap_mask<N>(p, mk);
-                    float o = bias3;
-#pragma unroll
-                    for (int tap = 0; tap < 27; ++tap) {
-                        const int q = p + Tile<N>::off(tap);
-                        const int qc = q < 0 ? 0 : (q >= P ? P - 1 : q);
-                        o = fmaf(mk[tap], (float)yb[qc * 32 + tap], o);
-                    }
-                    odd[k] += sgn ? -0.5f * o : 0.5f * o;
+                for (int tap = 0; tap < 27; ++tap) {
+                    const bool in = (inmask >> tap) & 1u;
+                    const float yv = (float)yb[tap * YP + (in ? tid + Tile<N>::off(tap) : tid)];
+                    o = in ? o + yv : o;
                 }
+                odd += sgn ? -0.5f * o : 0.5f * o;
             }
-            __syncthreads();
-            // the layer-3 table overwrote part of a1's zero halo: restore it
-            for (int i = l; i < RT * 16 * 32 / 16; i += 64)
-                if (T::halo(i))
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) a1b[i * 4 + k] = zero4;
-            __syncthreads();
+            // the next writes of x0b, a1 and yb come after the barrier at the top of the
+            // next evaluation (x0b) or after further barriers (a1, yb)
         }
         // averaged scatter
-#pragma unroll
-        for (int k = 0; k < NPL; ++k)
-            if (l + 64 * k < P) unsafeAtomicAdd(z + gi[k], (double)odd[k] * sc * scale * inv_mult[gi[k]]);
+        if (own) unsafeAtomicAdd(z + gi, (double)odd * sc * scale * inv_mult[gi]);
     }
 }
 
@@ -799,11 +810,11 @@ hipError_t nn_infer16(int n, int64_t nelem, const float *params, void *wpack, co
     if (nelem <= 0) return hipSuccess;
     h4_t *wp = static_cast<h4_t *>(wpack);
     hipLaunchKernelGGL(k_pack16, dim3((kPackSteps * 64 + 255) / 256), dim3(256), 0, s, params, wp);
-    // persistent waves: enough to fill every CU several times over
+    // persistent workgroups (one element at a time each): enough to fill every CU several times over
     const unsigned nb = (unsigned)std::min<int64_t>(nelem, 256 * 8);
-    if (n == 3) hipLaunchKernelGGL(k_net16<3>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
-    else if (n == 4) hipLaunchKernelGGL(k_net16<4>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
-    else if (n == 5) hipLaunchKernelGGL(k_net16<5>, dim3(nb), dim3(64), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
+    if (n == 3) hipLaunchKernelGGL(k_net16<3>, dim3(nb), dim3(256), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
+    else if (n == 4) hipLaunchKernelGGL(k_net16<4>, dim3(nb), dim3(256), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
+    else if (n == 5) hipLaunchKernelGGL(k_net16<5>, dim3(nb), dim3(256), 0, s, nelem, r, emap, logk, wp, params, inv_mult, scale, z);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
