@@ -505,21 +505,25 @@ __global__ __launch_bounds__(kCoarseThreads) void k_cpcg_b(int64_t n1, const dou
 
 // ---------------------------------------------------------------- FP16 MFMA inference
 // The whole network part z += W G^T (s_e NN(G_e r / s_e, log kappa_e)) for one element per
-// wave: gather and RMS-normalise the residual tile, three convolutions as implicit GEMMs
-// on v_mfma_f32_16x16x16f16 (FP16 operands, FP32 accumulation), and the averaged scatter.
-// GEMM rows are tile points (16 per row tile), columns output channels, and one k-step of
-// 16 is one tap's 16 input channels (layer 1: four taps of the two input channels padded
-// to four).  Lane layout (pinned by the 16-bit lane-layout test): A lane l holds
-// A[l%16][4(l/16)+t], B lane l holds B[4(l/16)+t][l%16], result lane l element v is
-// D[4(l/16)+v][l%16].  Activations live in LDS as [padded point][channel] FP16 on the
-// (N+2)^3 grid with a zero halo, so every shifted A-operand read is one 8-byte load.
-// Layer 3 (16 -> 1) is Y[pt][tap] = sum_c a2[pt][c] W3[c][tap] on MFMA followed by
-// out[pt] = b3 + sum_tap Y[pt + off(tap)][tap] over the taps that stay in the tile.
+// workgroup: gather and RMS-normalise the residual tile, three convolutions as implicit
+// GEMMs on v_mfma_f32_16x16x16f16 (FP16 operands, FP32 accumulation), and the averaged
+// scatter.  Layers 1 and 2 compute Y^T = W^T X^T: GEMM rows are the 16 output channels,
+// columns 16 tile points (one row tile of the tile), and one k-step of 16 is one tap's 16
+// input channels (layer 1: four taps of the two input channels padded to four).  Lane
+// layout (pinned by the 16-bit lane-layout test): A lane l holds A[l%16][4(l/16)+t], B
+// lane l holds B[4(l/16)+t][l%16], result lane l element v is D[4(l/16)+v][l%16], so a
+// lane reads and writes four consecutive channels of one point.  Activations live in LDS
+// as [padded point][channel] FP16 on the (N+2)^3 grid with a zero halo, so every shifted
+// operand read is one 8-byte load.  Layer 3 (16 -> 1) is Y[pt][tap] = sum_c a2[pt][c]
+// W3[c][tap] on MFMA followed by out[pt] = b3 + sum_tap Y[pt + off(tap)][tap] over the taps
+// that stay in the tile.
 typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 constexpr int kPackL1 = 7, kPackL2 = 27, kPackL3 = 2, kPackSteps = kPackL1 + kPackL2 + kPackL3;
 
-// B-operand tables in lane order: step s, lane l -> 4 halves (rows 4(l/16)+t, column l%16).
+// Weight tables in lane order: step s, lane l -> 4 halves, entry (k = 4(l/16)+t, output
+// channel l%16): the A-operand of layers 1-2 (row = output channel) and the B-operand of
+// layer 3 (column = tap).
 __global__ void k_pack16(const float *__restrict__ prm, h4_t *__restrict__ wp)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -585,7 +589,6 @@ __global__ __launch_bounds__(256, 3) void k_net16(int64_t nelem, const double *_
     __shared__ h4_t a2b[NP3 * 4];
     __shared__ _Float16 yb[32 * YP];  // layer-3 table [tap][row]
     __shared__ double red[4];
-    _Float16 *a1h = reinterpret_cast<_Float16 *>(a1b), *a2h = reinterpret_cast<_Float16 *>(a2b);
     const int tid = threadIdx.x, l = tid & 63, g = l >> 4, col = l & 15;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const h4_t zero4 = {0, 0, 0, 0};
@@ -601,23 +604,28 @@ __global__ __launch_bounds__(256, 3) void k_net16(int64_t nelem, const double *_
     for (int s = 0; s < kPackL2; ++s) w2[s] = wp[(kPackL1 + s) * 64 + l];
 #pragma unroll
     for (int s = 0; s < kPackL3; ++s) w3[s] = wp[(kPackL1 + kPackL2 + s) * 64 + l];
-    const float bias1 = prm[kNetOffB1 + col], bias2 = prm[kNetOffB2 + col], bias3 = prm[kNetOffB3];
+    // Layers 1 and 2 run transposed (D^T = W^T X^T: the packed weights as the A-operand, the
+    // activations as the B-operand), so each lane ends with four consecutive output
+    // channels 4g..4g+3 of one tile point and stores them with one 8-byte write.
+    float bias1[4], bias2[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        bias1[v] = prm[kNetOffB1 + 4 * g + v];
+        bias2[v] = prm[kNetOffB2 + 4 * g + v];
+    }
+    const float bias3 = prm[kNetOffB3];
     constexpr int MT = (RT + 3) / 4;  // row tiles per wave (the last ones may be absent)
     // A wave's tiles past RT (only when RT is not a multiple of 4) compute on clamped rows
     // and store nothing: the MFMA loops carry no per-tile branches.
     int rb[MT];                        // padded index of this lane's A-operand row (dummy rows repeat the last point)
-    int op[MT][4];                     // padded index of each result row this lane holds, -1 past the tile
+    int op[MT];                        // padded index of the point whose channels this lane stores, -1 past the tile
     bool tv[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const int rt = wave + 4 * m;
         tv[m] = rt < RT;
         rb[m] = T::pad(min(16 * rt + col, P - 1));
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int p = 16 * rt + 4 * g + v;
-            op[m][v] = (tv[m] && p < P) ? T::pad(p) : -1;
-        }
+        op[m] = (tv[m] && 16 * rt + col < P) ? rb[m] : -1;
     }
     int o1[kPackL1];  // layer-1 tap offset of this lane's k-group in every k-step (taps past 26: zero weights)
 #pragma unroll
@@ -672,12 +680,15 @@ __global__ __launch_bounds__(256, 3) void k_net16(int64_t nelem, const double *_
             for (int s = 0; s < kPackL1; ++s)
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(x0b[rb[m] + o1[s]], w1[s], acc[m], 0, 0, 0);
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(w1[s], x0b[rb[m] + o1[s]], acc[m], 0, 0, 0);
 #pragma unroll
             for (int m = 0; m < MT; ++m)
+                if (op[m] >= 0) {
+                    h4_t h;
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (op[m][v] >= 0) a1h[op[m][v] * 16 + col] = (_Float16)fmaxf(acc[m][v] + bias1, 0.f);
+                    for (int v = 0; v < 4; ++v) h[v] = (_Float16)fmaxf(acc[m][v] + bias1[v], 0.f);
+                    a1b[op[m] * 4 + g] = h;
+                }
             __syncthreads();
             // layer 2: 16 -> 16, one tap per k-step, ReLU; the taps in three chunks of nine so
             // that the compiler keeps at most a chunk's operand loads in flight (registers)
@@ -690,14 +701,17 @@ __global__ __launch_bounds__(256, 3) void k_net16(int64_t nelem, const double *_
                 for (int s = s0; s < s0 + 9; ++s)
 #pragma unroll
                     for (int m = 0; m < MT; ++m)
-                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(a1b[(rb[m] + T::off(s)) * 4 + g], w2[s],
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(w2[s], a1b[(rb[m] + T::off(s)) * 4 + g],
                                                                        acc[m], 0, 0, 0);
             }
 #pragma unroll
             for (int m = 0; m < MT; ++m)
+                if (op[m] >= 0) {
+                    h4_t h;
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (op[m][v] >= 0) a2h[op[m][v] * 16 + col] = (_Float16)fmaxf(acc[m][v] + bias2, 0.f);
+                    for (int v = 0; v < 4; ++v) h[v] = (_Float16)fmaxf(acc[m][v] + bias2[v], 0.f);
+                    a2b[op[m] * 4 + g] = h;
+                }
             __syncthreads();
             // layer 3, part 1: Y[pt][tap] for every tile point and tap (rows past the tile unused)
 #pragma unroll
