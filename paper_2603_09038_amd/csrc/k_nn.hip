@@ -568,7 +568,7 @@ struct Pad {
 };
 
 template <int N>
-__global__ __launch_bounds__(256, 3) void k_net16(int64_t nelem, const double *__restrict__ r,
+__global__ __launch_bounds__(256, 2) void k_net16(int64_t nelem, const double *__restrict__ r,
                                                   const int32_t *__restrict__ emap, const float *__restrict__ logk,
                                                   const h4_t *__restrict__ wp, const float *__restrict__ prm,
                                                   const double *__restrict__ inv_mult, double scale,
@@ -690,15 +690,16 @@ __global__ __launch_bounds__(256, 3) void k_net16(int64_t nelem, const double *_
                     a1b[op[m] * 4 + g] = h;
                 }
             __syncthreads();
-            // layer 2: 16 -> 16, one tap per k-step, ReLU; the taps in three chunks of nine so
-            // that the compiler keeps at most a chunk's operand loads in flight (registers)
+            // layer 2: 16 -> 16, one tap per k-step, ReLU; a compiler barrier before each tap
+            // keeps the compiler from hoisting all 27 taps' operand loads (registers): measured
+            // faster than chunks of 3, 9 or 27 taps
 #pragma unroll
             for (int m = 0; m < MT; ++m) acc[m] = (f4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s0 = 0; s0 < 27; s0 += 9) {
+            for (int s0 = 0; s0 < 27; s0 += 1) {
                 asm volatile("" ::: "memory");
 #pragma unroll
-                for (int s = s0; s < s0 + 9; ++s)
+                for (int s = s0; s < s0 + 1; ++s)
 #pragma unroll
                     for (int m = 0; m < MT; ++m)
                         acc[m] = __builtin_amdgcn_mfma_f32_16x16x16f16(w2[s], a1b[(rb[m] + T::off(s)) * 4 + g],
