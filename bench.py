@@ -245,7 +245,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--learned-train", type=int, default=40, help="training draws of the learned preconditioner")
-    ap.add_argument("--learned-held", type=int, default=4, help="held-out draws of the learned comparison")
+    ap.add_argument("--learned-held", type=int, default=20, help="held-out draws of the learned comparison")
     ap.add_argument("--learned-weights", default=None, help="load parameters from this file instead of training")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (for HBM counter calibration)")
