@@ -315,6 +315,20 @@ def main():
                      "kernel_gdofs": ndof / (k_mean_ms * 1e-3) / 1e9,
                      "fp64_frac": alg_flops(nelem, p, q, 2) / (k_mean_ms * 1e-3) / 78.6e12},
     }
+    # the paper's kernel matrix at this workload: {fused, unfused} x {vector ALU, MFMA}; the
+    # unfused apply moves the quadrature-point tensor through HBM four more times
+    qt_bytes = 8 * 3 * q ** 3 * nelem
+    matrix = []
+    for name, v in (("fused_valu", hexpa.PA_VARIANT_VALU), ("fused_mfma", hexpa.PA_VARIANT_MFMA),
+                    ("unfused_valu", hexpa.PA_VARIANT_VALU_UNFUSED), ("unfused_mfma", hexpa.PA_VARIANT_MFMA_UNFUSED)):
+        op.set_variant(v)
+        km, _ = time_kernel(op, hexpa, x, y, 30, 10)
+        hb = ab + (4 * qt_bytes if name.startswith("unfused") else 0)
+        matrix.append({"variant": name, "ms": km, "gdofs": ndof / (km * 1e-3) / 1e9, "hbm_bytes_model": hb,
+                       "hbm_frac_model": hb / (km * 1e-3) / 1e9 / HBM_PEAK_GBS})
+        log(f"kernel matrix {name}: {km:.4f} ms")
+    op.set_variant(VAR[used])
+    out["kernel_matrix"] = matrix
     if not args.no_cg:
         out["cg"] = run_cg(hexpa, mesh, coeff, p, q)
         log(f"C2 Jacobi-PCG: {out['cg']['iters']} iterations, {out['cg']['seconds']:.3f} s")

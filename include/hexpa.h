@@ -84,6 +84,11 @@ typedef struct {
 #define PA_VARIANT_VALU 1    /* fused kernel, FP64 vector-ALU contractions, atomic scatter */
 #define PA_VARIANT_MFMA_COLORED 2 /* MFMA contractions, 8 colour launches, plain read-modify-write
                                      scatter: bitwise reproducible */
+#define PA_VARIANT_MFMA_UNFUSED 3 /* unfused: forward contractions, D and transposed contractions
+                                     as three kernels through an HBM buffer of the quadrature-point
+                                     tensor (handle-owned, allocated on first use: nelem x
+                                     (3 | 1 | 4) x Q^3 doubles); FP64 MFMA contractions */
+#define PA_VARIANT_VALU_UNFUSED 4 /* the same with FP64 vector-ALU contractions */
 
 typedef struct pa_op pa_op;
 

@@ -80,6 +80,7 @@ extern "C" void pa_destroy(pa_op *op)
     dfree(op->d_elem_dofs);
     dfree(op->d_qdata);
     dfree(op->d_qdata32);
+    dfree(op->d_qbuf);
     dfree(op->d_vert);
     dfree(op->d_hex);
     dfree(op->d_tab);
@@ -260,6 +261,10 @@ int hexpa::do_apply(pa_op *op, int variant, const double *x, double *y, hipStrea
             HIP_OK(launch_apply(op, variant, x, y, op->d_color_elems + op->color_off[c], n, s, &ok));
         }
     } else {
+        if ((variant == PA_VARIANT_MFMA_UNFUSED || variant == PA_VARIANT_VALU_UNFUSED) && !op->d_qbuf) {
+            const int ng = (op->ops & 2) ? ((op->ops & 1) ? 4 : 3) : 1;
+            HIP_OK(dalloc(&op->d_qbuf, (size_t)op->nelem * ng * op->q * op->q * op->q));
+        }
         HIP_OK(launch_apply(op, variant, x, y, nullptr, op->nelem, s, &ok));
     }
     if (!ok) {
@@ -368,7 +373,7 @@ extern "C" int pa_get_ess(pa_op *op, int32_t *host_out)
 extern "C" int pa_set_variant(pa_op *op, int variant)
 {
     if (!op) return arg_error("pa_set_variant: NULL op");
-    if (variant < PA_VARIANT_MFMA || variant > PA_VARIANT_MFMA_COLORED) return arg_error("pa_set_variant: unknown variant");
+    if (variant < PA_VARIANT_MFMA || variant > PA_VARIANT_VALU_UNFUSED) return arg_error("pa_set_variant: unknown variant");
     if (variant == PA_VARIANT_MFMA_COLORED && !op->d_color_elems) {
         set_error("pa_set_variant: coloured apply needs a structured box mesh");
         return PA_ERR_UNSUPPORTED;

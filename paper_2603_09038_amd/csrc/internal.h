@@ -52,6 +52,7 @@ struct pa_op {
     int32_t *d_elem_dofs = nullptr;  // [nelem][d^3]
     double *d_qdata = nullptr;       // [nelem][ncomp][q^3]
     float *d_qdata32 = nullptr;      // FP32 copy of D for the mixed-precision apply (lazy)
+    double *d_qbuf = nullptr;        // quadrature-point tensor of the unfused apply (lazy)
     double *d_vert = nullptr;        // [nvert][3]
     int32_t *d_hex = nullptr;        // [nelem][8]
     int nvert = 0;

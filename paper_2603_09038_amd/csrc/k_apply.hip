@@ -142,11 +142,17 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
     }
 }
 
-template <int D, int Q, int OPS, int EX, bool ATOMIC>
+// STAGE 0: the fused apply.  The unfused apply (the paper's baseline that fusion is
+// measured against) runs the same code in three launches through HBM: STAGE 1 gathers x,
+// runs the forward contractions and writes the quadrature-point tensor of every element to
+// qbuf [e][channel][Q^3]; k_dstep applies D there in place; STAGE 2 reads it back, runs the
+// transposed contractions and scatters into y.
+template <int D, int Q, int OPS, int EX, bool ATOMIC, int STAGE = 0>
 __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_apply(
     int nelem, int ngroups, const int32_t *__restrict__ elist, const int32_t *__restrict__ emap,
     const typename ExT<EX>::T *__restrict__ qd, const DevTables *__restrict__ tab,
-    const typename ExT<EX>::T *__restrict__ x, typename ExT<EX>::T *__restrict__ y)
+    const typename ExT<EX>::T *__restrict__ x, typename ExT<EX>::T *__restrict__ y,
+    typename ExT<EX>::T *__restrict__ qbuf)
 {
     using T = typename ExT<EX>::T;
     using CFG = ApplyCfg<D, OPS, EX>;
@@ -188,14 +194,16 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     }
     if (g >= gend) return;
 
+    constexpr bool FWD = STAGE != 2, DSTEP = STAGE == 0;
+    constexpr int QT = S::NG * Q3;  // quadrature-point tensor per element (unfused stages)
     T dq[NS][NC];
     int32_t mcur[NM];
     T xcur[NM];
     {
         const int e0 = g * E, nv = min(E, nelem - e0);
-        if constexpr (!kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
+        if constexpr (DSTEP && !kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
         load_map<S, EL>(mcur, emap, elist, e0, nv, tid);
-        load_x<S>(xcur, mcur, x);
+        if constexpr (FWD) load_x<S>(xcur, mcur, x);
     }
 
     for (;;) {
@@ -211,9 +219,14 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
             if (L < E * D3) {
                 const int e = L / D3, I = L - e * D3;
                 lmap[L] = mcur[s];
-                bufA[e * S::SZ_A + I] = xcur[s];
+                if constexpr (FWD) bufA[e * S::SZ_A + I] = xcur[s];
             }
         }
+        if constexpr (!FWD)  // the quadrature-point tensor, D already applied by k_dstep
+            for (int L = tid; L < nv * QT; L += NT) {
+                const int e = L / QT, r = L - e * QT;
+                bufB[e * S::SZ_B + r] = qbuf[(int64_t)(e0 + e) * QT + r];
+            }
         int32_t mnext[NM];
         load_map<S, EL>(mnext, emap, elist, e0n, nvn, tid);
         T dnext[kPrefetchD ? NS : 1][NC];
@@ -221,7 +234,8 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         lds_barrier();
 
         // forward contractions
-        if constexpr (S::kDiff) {
+        if constexpr (!FWD) {
+        } else if constexpr (S::kDiff) {
             run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
             lds_barrier();
             if constexpr (PAIRS) {  // the two independent y passes on one wave each
@@ -246,13 +260,28 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         }
         // the next group's map has had the forward passes to arrive: start its x gather
         T xnext[NM];
-        load_x<S>(xnext, mnext, x);
+        if constexpr (FWD) load_x<S>(xnext, mnext, x);
         lds_barrier();
+        if constexpr (STAGE == 1) {  // the quadrature-point tensor goes to HBM; next group
+            for (int L = tid; L < nv * QT; L += NT) {
+                const int e = L / QT, r = L - e * QT;
+                qbuf[(int64_t)(e0 + e) * QT + r] = bufB[e * S::SZ_B + r];
+            }
+            if (!more) break;
+            lds_barrier();
+            g = gn;
+#pragma unroll
+            for (int s = 0; s < NM; ++s) {
+                mcur[s] = mnext[s];
+                xcur[s] = xnext[s];
+            }
+            continue;
+        }
 
         // D at quadrature points: v = D grad_ref u (symmetric 3x3) and/or v_u = D_m u
-        if constexpr (kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
+        if constexpr (DSTEP && kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
+        for (int s = 0; s < (DSTEP ? NS : 0); ++s) {
             const int L = tid + s * NT;
             if (L < E * Q3) {
                 const int e = L / Q3, r = L - e * Q3;
@@ -270,7 +299,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
                 }
             }
         }
-        if (more && !kLateD) {
+        if (DSTEP && more && !kLateD) {
             if constexpr (kPrefetchD) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
@@ -316,7 +345,34 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
 #pragma unroll
         for (int s = 0; s < NM; ++s) {
             mcur[s] = mnext[s];
-            xcur[s] = xnext[s];
+            if constexpr (FWD) xcur[s] = xnext[s];
+        }
+    }
+}
+
+// D-step of the unfused apply, in place on the quadrature-point tensor [e][channel][Q^3]
+// (channels as in the fused kernel: dx, dy, (u,) dz for diffusion; u for mass).
+template <int Q, int OPS, class T>
+__global__ __launch_bounds__(256) void k_dstep(int64_t npts, const T *__restrict__ qd, T *__restrict__ qbuf)
+{
+    using S = Shape<2, Q, OPS, (int)sizeof(T)>;  // channel counts only (independent of D)
+    constexpr int Q3 = Q * Q * Q, NG = S::NG, NC = S::NCOMP;
+    constexpr bool M = S::kMass;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i / Q3;
+        const int r = (int)(i - e * Q3);
+        T *V = qbuf + e * (NG * Q3) + r;
+        const T *Dm = qd + e * (NC * Q3) + r;
+        if constexpr (S::kDiff) {
+            using CH = Chan<Q, M>;
+            const T g0 = V[CH::X], g1 = V[CH::Y], g2 = V[CH::Z];
+            const T d0 = Dm[0], d1 = Dm[Q3], d2 = Dm[2 * Q3], d3 = Dm[3 * Q3], d4 = Dm[4 * Q3], d5 = Dm[5 * Q3];
+            V[CH::X] = d0 * g0 + d1 * g1 + d2 * g2;
+            V[CH::Y] = d1 * g0 + d3 * g1 + d4 * g2;
+            V[CH::Z] = d2 * g0 + d4 * g1 + d5 * g2;
+            if constexpr (M) V[CH::V] = Dm[6 * Q3] * V[CH::V];
+        } else {
+            V[0] *= Dm[0];
         }
     }
 }
@@ -583,6 +639,47 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
 }
 
 // ------------------------------------------------------------------ launchers
+// grid of a persistent kernel: resident capacity (queried once per kernel: the template
+// parameter is the kernel itself, so each has its own cached value), at most ngroups
+template <auto KERN>
+static int persistent_blocks(int nt, int ngroups)
+{
+    const auto kern = KERN;
+    if (kOversub <= 0) return ngroups;
+    static int cap = 0;
+    if (cap == 0) {
+        int per_cu = 0, dev = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+            ncu = 256;
+        cap = per_cu * ncu * kOversub;
+    }
+    return ngroups < cap ? ngroups : cap;
+}
+
+// The unfused apply: forward stage, D-step, transposed stage (y must hold zeros).
+template <int D, int Q, int OPS, int EX>
+static hipError_t launch_unfused(const pa_op *op, const double *x, double *y, double *qbuf, hipStream_t s)
+{
+    using CFG = ApplyCfg<D, OPS, EX>;
+    using S = Shape<D, Q, OPS, 8, CFG::NT, CFG::BUDGET>;
+    const int n = op->nelem;
+    const int ngroups = (n + S::E - 1) / S::E;
+    if (ngroups == 0) return hipSuccess;
+    constexpr auto k1 = k_apply<D, Q, OPS, EX, true, 1>;
+    constexpr auto k3 = k_apply<D, Q, OPS, EX, true, 2>;
+    hipLaunchKernelGGL(k1, dim3(persistent_blocks<k1>(CFG::NT, ngroups)), dim3(CFG::NT), 0, s, n, ngroups,
+                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf);
+    const int64_t npts = (int64_t)n * S::Q3;
+    auto k2 = k_dstep<Q, OPS, double>;
+    hipLaunchKernelGGL(k2, dim3((unsigned)std::min<int64_t>((npts + 255) / 256, 65536)), dim3(256), 0, s, npts,
+                       (const double *)op->d_qdata, qbuf);
+    hipLaunchKernelGGL(k3, dim3(persistent_blocks<k3>(CFG::NT, ngroups)), dim3(CFG::NT), 0, s, n, ngroups,
+                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf);
+    return hipGetLastError();
+}
+
 template <int D, int Q, int OPS, int EX, bool ATOMIC>
 static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const typename ExT<EX>::T *x,
                            typename ExT<EX>::T *y, const int32_t *elist, int n, hipStream_t s)
@@ -595,26 +692,17 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
     constexpr int NT = DMA ? kThreads : CFG::NT;
     const int ngroups = (n + EG - 1) / EG;
     if (ngroups == 0) return hipSuccess;
-    void (*kern)(int, int, const int32_t *, const int32_t *, const T *, const DevTables *, const T *, T *);
-    if constexpr (DMA) kern = k_apply_dma<D, Q, OPS, EX, ATOMIC>;
-    else kern = k_apply<D, Q, OPS, EX, ATOMIC>;
-    int nblocks = ngroups;
-    if (kOversub > 0) {
-        // resident capacity of the device for this kernel (queried once)
-        static int cap = 0;
-        if (cap == 0) {
-            int per_cu = 0, dev = 0, ncu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0) != hipSuccess || per_cu < 1)
-                per_cu = 1;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
-                ncu = 256;
-            cap = per_cu * ncu * kOversub;
-        }
-        nblocks = ngroups < cap ? ngroups : cap;
+    if constexpr (!DMA) {
+        constexpr auto kern = k_apply<D, Q, OPS, EX, ATOMIC, 0>;
+        const int nblocks = persistent_blocks<kern>(NT, ngroups);
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab, x,
+                           y, (T *)nullptr);
+    } else {
+        constexpr auto kern = k_apply_dma<D, Q, OPS, EX, ATOMIC>;
+        const int nblocks = persistent_blocks<kern>(NT, ngroups);
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab, x,
+                           y);
     }
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab,
-                       x, y);
     return hipGetLastError();
 }
 
@@ -623,6 +711,8 @@ static hipError_t launch_t(const pa_op *op, int variant, const double *x, double
                            hipStream_t s)
 {
     switch (variant) {
+    case PA_VARIANT_MFMA_UNFUSED: return launch_unfused<D, Q, OPS, EX_MFMA64>(op, x, y, op->d_qbuf, s);
+    case PA_VARIANT_VALU_UNFUSED: return launch_unfused<D, Q, OPS, EX_VALU64>(op, x, y, op->d_qbuf, s);
     case PA_VARIANT_VALU: return launch_k<D, Q, OPS, EX_VALU64, true>(op, op->d_qdata, x, y, elist, n, s);
     case PA_VARIANT_MFMA_COLORED: return launch_k<D, Q, OPS, EX_MFMA64, false>(op, op->d_qdata, x, y, elist, n, s);
     default: return launch_k<D, Q, OPS, EX_MFMA64, true>(op, op->d_qdata, x, y, elist, n, s);

@@ -118,7 +118,8 @@ def test_c1_parity(hx, ops):
     assert op.ndof == 729
     x = synth.rand_x(op.ndof, 0)
     ref = oracle.Problem(mesh, 2, 4, ops=_ops_o(ops)).apply(x)
-    for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU, hx.PA_VARIANT_MFMA_COLORED):
+    for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU, hx.PA_VARIANT_MFMA_COLORED, hx.PA_VARIANT_MFMA_UNFUSED,
+                    hx.PA_VARIANT_VALU_UNFUSED):
         op.set_variant(variant)
         y = op.apply(_cuda(x)).cpu().numpy()
         assert _rel(y, ref) <= TOL, (variant, _rel(y, ref))
@@ -138,7 +139,8 @@ def test_apply_parity_orders(hx, p, dq):
         op = hx.PAOperator(mesh, p, q, coeff=coeff, ops=ops)
         x = synth.rand_x(op.ndof, p)
         ref = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.sine(), ops=_ops_o(ops)).apply(x)
-        for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU):
+        for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU, hx.PA_VARIANT_MFMA_UNFUSED,
+                        hx.PA_VARIANT_VALU_UNFUSED):
             op.set_variant(variant)
             y = op.apply(_cuda(x)).cpu().numpy()
             assert _rel(y, ref) <= TOL, (p, q, ops, variant, _rel(y, ref))
