@@ -315,15 +315,18 @@ def main():
                      "kernel_gdofs": ndof / (k_mean_ms * 1e-3) / 1e9,
                      "fp64_frac": alg_flops(nelem, p, q, 2) / (k_mean_ms * 1e-3) / 78.6e12},
     }
-    # the paper's kernel matrix at this workload: {fused, unfused} x {vector ALU, MFMA}; the
-    # unfused apply moves the quadrature-point tensor through HBM four more times
+    # the paper's kernel matrix at this workload: {unfused PA, fused PA, fused matrix-free} x
+    # {vector ALU, MFMA}; the unfused apply moves the quadrature-point tensor through HBM four
+    # more times, the matrix-free one reads no D (vertex coordinates instead)
     qt_bytes = 8 * 3 * q ** 3 * nelem
     matrix = []
+    mf_bytes = ab - 8 * 6 * q ** 3 * nelem + nelem * (8 * 4 + 24 * 8)  # no D; hex indices + vertex coordinates
     for name, v in (("fused_valu", hexpa.PA_VARIANT_VALU), ("fused_mfma", hexpa.PA_VARIANT_MFMA),
-                    ("unfused_valu", hexpa.PA_VARIANT_VALU_UNFUSED), ("unfused_mfma", hexpa.PA_VARIANT_MFMA_UNFUSED)):
+                    ("unfused_valu", hexpa.PA_VARIANT_VALU_UNFUSED), ("unfused_mfma", hexpa.PA_VARIANT_MFMA_UNFUSED),
+                    ("fused_mf_valu", hexpa.PA_VARIANT_VALU_MF), ("fused_mf_mfma", hexpa.PA_VARIANT_MFMA_MF)):
         op.set_variant(v)
         km, _ = time_kernel(op, hexpa, x, y, 30, 10)
-        hb = ab + (4 * qt_bytes if name.startswith("unfused") else 0)
+        hb = ab + 4 * qt_bytes if name.startswith("unfused") else (mf_bytes if "_mf_" in name else ab)
         matrix.append({"variant": name, "ms": km, "gdofs": ndof / (km * 1e-3) / 1e9, "hbm_bytes_model": hb,
                        "hbm_frac_model": hb / (km * 1e-3) / 1e9 / HBM_PEAK_GBS})
         log(f"kernel matrix {name}: {km:.4f} ms")

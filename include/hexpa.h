@@ -89,6 +89,10 @@ typedef struct {
                                      tensor (handle-owned, allocated on first use: nelem x
                                      (3 | 1 | 4) x Q^3 doubles); FP64 MFMA contractions */
 #define PA_VARIANT_VALU_UNFUSED 4 /* the same with FP64 vector-ALU contractions */
+#define PA_VARIANT_MFMA_MF 5      /* fused matrix-free: no stored D; the kernel recomputes D at each
+                                     quadrature point from the element's vertices and the coefficient
+                                     (the setup kernel's arithmetic); FP64 MFMA contractions */
+#define PA_VARIANT_VALU_MF 6      /* the same with FP64 vector-ALU contractions */
 
 typedef struct pa_op pa_op;
 

@@ -373,7 +373,7 @@ extern "C" int pa_get_ess(pa_op *op, int32_t *host_out)
 extern "C" int pa_set_variant(pa_op *op, int variant)
 {
     if (!op) return arg_error("pa_set_variant: NULL op");
-    if (variant < PA_VARIANT_MFMA || variant > PA_VARIANT_VALU_UNFUSED) return arg_error("pa_set_variant: unknown variant");
+    if (variant < PA_VARIANT_MFMA || variant > PA_VARIANT_VALU_MF) return arg_error("pa_set_variant: unknown variant");
     if (variant == PA_VARIANT_MFMA_COLORED && !op->d_color_elems) {
         set_error("pa_set_variant: coloured apply needs a structured box mesh");
         return PA_ERR_UNSUPPORTED;

@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "apply_passes.h"
+#include "geometry.h"
 
 #ifndef HEXPA_PREFETCH_D
 #define HEXPA_PREFETCH_D 0
@@ -146,13 +147,16 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
 // measured against) runs the same code in three launches through HBM: STAGE 1 gathers x,
 // runs the forward contractions and writes the quadrature-point tensor of every element to
 // qbuf [e][channel][Q^3]; k_dstep applies D there in place; STAGE 2 reads it back, runs the
-// transposed contractions and scatters into y.
+// transposed contractions and scatters into y.  STAGE 3 is the fused matrix-free apply:
+// no stored D; the D-step recomputes it at every quadrature point from the element's eight
+// vertices (staged in LDS per group) and the coefficient, with the setup kernel's code.
 template <int D, int Q, int OPS, int EX, bool ATOMIC, int STAGE = 0>
 __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_apply(
     int nelem, int ngroups, const int32_t *__restrict__ elist, const int32_t *__restrict__ emap,
     const typename ExT<EX>::T *__restrict__ qd, const DevTables *__restrict__ tab,
     const typename ExT<EX>::T *__restrict__ x, typename ExT<EX>::T *__restrict__ y,
-    typename ExT<EX>::T *__restrict__ qbuf)
+    typename ExT<EX>::T *__restrict__ qbuf, const double *__restrict__ vert, const int32_t *__restrict__ hex,
+    CoeffDev cf)
 {
     using T = typename ExT<EX>::T;
     using CFG = ApplyCfg<D, OPS, EX>;
@@ -194,14 +198,15 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     }
     if (g >= gend) return;
 
-    constexpr bool FWD = STAGE != 2, DSTEP = STAGE == 0;
+    constexpr bool FWD = STAGE != 2, MF = STAGE == 3, DSTEP = STAGE == 0 || MF, LOADD = STAGE == 0;
+    __shared__ double vxs[MF ? E * 24 : 1];  // vertex coordinates of the group's elements (MF)
     constexpr int QT = S::NG * Q3;  // quadrature-point tensor per element (unfused stages)
     T dq[NS][NC];
     int32_t mcur[NM];
     T xcur[NM];
     {
         const int e0 = g * E, nv = min(E, nelem - e0);
-        if constexpr (DSTEP && !kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
+        if constexpr (LOADD && !kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
         load_map<S, EL>(mcur, emap, elist, e0, nv, tid);
         if constexpr (FWD) load_x<S>(xcur, mcur, x);
     }
@@ -222,6 +227,12 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
                 if constexpr (FWD) bufA[e * S::SZ_A + I] = xcur[s];
             }
         }
+        if constexpr (MF)
+            for (int L = tid; L < nv * 24; L += NT) {
+                const int e = L / 24, c = (L - e * 24) / 3, r = L - e * 24 - 3 * c;
+                const int64_t ge = EL ? elist[e0 + e] : e0 + e;
+                vxs[L] = vert[(int64_t)hex[ge * 8 + c] * 3 + r];
+            }
         if constexpr (!FWD)  // the quadrature-point tensor, D already applied by k_dstep
             for (int L = tid; L < nv * QT; L += NT) {
                 const int e = L / QT, r = L - e * QT;
@@ -279,14 +290,24 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         }
 
         // D at quadrature points: v = D grad_ref u (symmetric 3x3) and/or v_u = D_m u
-        if constexpr (DSTEP && kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
+        if constexpr (LOADD && kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
 #pragma unroll
         for (int s = 0; s < (DSTEP ? NS : 0); ++s) {
             const int L = tid + s * NT;
             if (L < E * Q3) {
                 const int e = L / Q3, r = L - e * Q3;
                 T *V = bufB + e * S::SZ_B + r;
-                const T *Dm = dq[s];
+                T dmf[MF ? NC : 1];
+                if constexpr (MF) {
+                    Hex h;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) h.X[c][k] = vxs[e * 24 + 3 * c + k];
+                    const int qa = r % Q, qb = (r / Q) % Q, qc = r / (Q * Q);
+                    qp_data<OPS>(h, stab.x[qa], stab.x[qb], stab.x[qc], stab.w[qa] * stab.w[qb] * stab.w[qc], cf, dmf);
+                }
+                const T *Dm = MF ? dmf : dq[s];
                 if constexpr (S::kDiff) {
                     using CH = Chan<Q, M>;
                     const T g0 = V[CH::X], g1 = V[CH::Y], g2 = V[CH::Z];
@@ -299,7 +320,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
                 }
             }
         }
-        if (DSTEP && more && !kLateD) {
+        if (LOADD && more && !kLateD) {
             if constexpr (kPrefetchD) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
@@ -670,13 +691,31 @@ static hipError_t launch_unfused(const pa_op *op, const double *x, double *y, do
     constexpr auto k1 = k_apply<D, Q, OPS, EX, true, 1>;
     constexpr auto k3 = k_apply<D, Q, OPS, EX, true, 2>;
     hipLaunchKernelGGL(k1, dim3(persistent_blocks<k1>(CFG::NT, ngroups)), dim3(CFG::NT), 0, s, n, ngroups,
-                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf);
+                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf, op->d_vert,
+                       op->d_hex, op->coeff);
     const int64_t npts = (int64_t)n * S::Q3;
     auto k2 = k_dstep<Q, OPS, double>;
     hipLaunchKernelGGL(k2, dim3((unsigned)std::min<int64_t>((npts + 255) / 256, 65536)), dim3(256), 0, s, npts,
                        (const double *)op->d_qdata, qbuf);
     hipLaunchKernelGGL(k3, dim3(persistent_blocks<k3>(CFG::NT, ngroups)), dim3(CFG::NT), 0, s, n, ngroups,
-                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf);
+                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf, op->d_vert,
+                       op->d_hex, op->coeff);
+    return hipGetLastError();
+}
+
+// The fused matrix-free apply (D recomputed in the kernel; y must hold zeros).
+template <int D, int Q, int OPS, int EX>
+static hipError_t launch_mf(const pa_op *op, const double *x, double *y, hipStream_t s)
+{
+    using CFG = ApplyCfg<D, OPS, EX>;
+    using S = Shape<D, Q, OPS, 8, CFG::NT, CFG::BUDGET>;
+    const int n = op->nelem;
+    const int ngroups = (n + S::E - 1) / S::E;
+    if (ngroups == 0) return hipSuccess;
+    constexpr auto k = k_apply<D, Q, OPS, EX, true, 3>;
+    hipLaunchKernelGGL(k, dim3(persistent_blocks<k>(CFG::NT, ngroups)), dim3(CFG::NT), 0, s, n, ngroups,
+                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, (double *)nullptr,
+                       op->d_vert, op->d_hex, op->coeff);
     return hipGetLastError();
 }
 
@@ -696,7 +735,7 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
         constexpr auto kern = k_apply<D, Q, OPS, EX, ATOMIC, 0>;
         const int nblocks = persistent_blocks<kern>(NT, ngroups);
         hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab, x,
-                           y, (T *)nullptr);
+                           y, (T *)nullptr, (const double *)nullptr, (const int32_t *)nullptr, CoeffDev{});
     } else {
         constexpr auto kern = k_apply_dma<D, Q, OPS, EX, ATOMIC>;
         const int nblocks = persistent_blocks<kern>(NT, ngroups);
@@ -713,6 +752,8 @@ static hipError_t launch_t(const pa_op *op, int variant, const double *x, double
     switch (variant) {
     case PA_VARIANT_MFMA_UNFUSED: return launch_unfused<D, Q, OPS, EX_MFMA64>(op, x, y, op->d_qbuf, s);
     case PA_VARIANT_VALU_UNFUSED: return launch_unfused<D, Q, OPS, EX_VALU64>(op, x, y, op->d_qbuf, s);
+    case PA_VARIANT_MFMA_MF: return launch_mf<D, Q, OPS, EX_MFMA64>(op, x, y, s);
+    case PA_VARIANT_VALU_MF: return launch_mf<D, Q, OPS, EX_VALU64>(op, x, y, s);
     case PA_VARIANT_VALU: return launch_k<D, Q, OPS, EX_VALU64, true>(op, op->d_qdata, x, y, elist, n, s);
     case PA_VARIANT_MFMA_COLORED: return launch_k<D, Q, OPS, EX_MFMA64, false>(op, op->d_qdata, x, y, elist, n, s);
     default: return launch_k<D, Q, OPS, EX_MFMA64, true>(op, op->d_qdata, x, y, elist, n, s);

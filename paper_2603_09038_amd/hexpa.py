@@ -20,6 +20,7 @@ PA_ERR_NOT_CONVERGED, PA_ERR_BREAKDOWN, PA_ERR_IO = -5, -6, -7
 PA_MASS, PA_DIFFUSION = 1, 2
 PA_COEFF_CONST, PA_COEFF_SINE, PA_COEFF_GRID = 0, 1, 2
 PA_VARIANT_MFMA, PA_VARIANT_VALU, PA_VARIANT_MFMA_COLORED, PA_VARIANT_MFMA_UNFUSED, PA_VARIANT_VALU_UNFUSED = 0, 1, 2, 3, 4
+PA_VARIANT_MFMA_MF, PA_VARIANT_VALU_MF = 5, 6
 PA_CG_PLAIN, PA_CG_JACOBI, PA_CG_MIXED_IR, PA_CG_FCG, PA_CG_MIXED_FCG, PA_CG_MIXED_RU = 0, 1, 2, 3, 4, 5
 PA_LP_LOSS_ENERGY, PA_LP_LOSS_L2 = 0, 1
 PA_LP_FP16, PA_LP_BF16 = 0, 1

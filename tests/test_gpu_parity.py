@@ -119,7 +119,7 @@ def test_c1_parity(hx, ops):
     x = synth.rand_x(op.ndof, 0)
     ref = oracle.Problem(mesh, 2, 4, ops=_ops_o(ops)).apply(x)
     for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU, hx.PA_VARIANT_MFMA_COLORED, hx.PA_VARIANT_MFMA_UNFUSED,
-                    hx.PA_VARIANT_VALU_UNFUSED):
+                    hx.PA_VARIANT_VALU_UNFUSED, hx.PA_VARIANT_MFMA_MF, hx.PA_VARIANT_VALU_MF):
         op.set_variant(variant)
         y = op.apply(_cuda(x)).cpu().numpy()
         assert _rel(y, ref) <= TOL, (variant, _rel(y, ref))
@@ -140,7 +140,7 @@ def test_apply_parity_orders(hx, p, dq):
         x = synth.rand_x(op.ndof, p)
         ref = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.sine(), ops=_ops_o(ops)).apply(x)
         for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU, hx.PA_VARIANT_MFMA_UNFUSED,
-                        hx.PA_VARIANT_VALU_UNFUSED):
+                        hx.PA_VARIANT_VALU_UNFUSED, hx.PA_VARIANT_MFMA_MF, hx.PA_VARIANT_VALU_MF):
             op.set_variant(variant)
             y = op.apply(_cuda(x)).cpu().numpy()
             assert _rel(y, ref) <= TOL, (p, q, ops, variant, _rel(y, ref))
@@ -155,6 +155,10 @@ def test_grid_coefficient_and_diag_load_points(hx):
     P = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.from_grid(grid), ops=3)
     x = synth.rand_x(op.ndof, 2)
     assert _rel(op.apply(_cuda(x)).cpu().numpy(), P.apply(x)) <= TOL
+    for variant in (hx.PA_VARIANT_MFMA_MF, hx.PA_VARIANT_VALU_MF):  # D recomputed from the grid coefficient
+        op.set_variant(variant)
+        assert _rel(op.apply(_cuda(x)).cpu().numpy(), P.apply(x)) <= TOL, variant
+    op.set_variant(hx.PA_VARIANT_MFMA)
     assert _rel(op.diag().cpu().numpy(), P.diag()) <= TOL
     xq = op.qpoints().cpu().numpy()
     np.testing.assert_allclose(xq, P.qpoints(), rtol=0, atol=1e-15)
