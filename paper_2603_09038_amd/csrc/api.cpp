@@ -389,13 +389,16 @@ extern "C" int pa_info(const pa_op *op, pa_info_t *info)
     info->ness = op->ness; info->ncomp = op->ncomp; info->variant = op->variant;
     const int d = op->d, q = op->q;
     const int ncomp = op->ncomp;
-    // elements per workgroup of the fused kernel (mirrors Shape<>::E)
+    // elements per workgroup of the register-staged fused kernel (mirrors Shape<>::E with
+    // the padded LDS tensors and the LDS budget of ApplyCfg)
     const bool diff = op->ops & PA_DIFFUSION, mass = op->ops & PA_MASS;
     const int ng = diff ? (mass ? 4 : 3) : 1;
+    const int dp = d % 4 ? d : d + 1, qp = q % 4 ? q : q + 1;  // pad_stride
     auto mx = [](int a, int b) { return a > b ? a : b; };
-    const int sa = mx(d * d * d, mx((diff ? 3 * q * q : q * q) * d, ng * q * q * d)) | 1;
-    const int sb = mx((diff ? 2 * q : q) * d * d, mx(ng * q * q * q, (diff ? 2 : 1) * d * d * q)) | 1;
-    int e = (48 * 1024) / (8 * (sa + sb) + 4 * d * d * d);
+    const int sa = mx(d * d * dp, mx((diff ? 3 * q * q : q * q) * dp, ng * q * qp * d)) | 1;
+    const int sb = mx((diff ? 2 * q : q) * d * dp, mx(ng * q * q * qp, (diff ? 2 : 1) * d * d * qp)) | 1;
+    const int budget = (diff && d <= 5) ? 24 * 1024 : 48 * 1024;
+    int e = budget / (8 * (sa + sb) + 4 * d * d * d);
     info->elems_per_block = e < 1 ? 1 : (e > 32 ? 32 : e);
     info->qdata_bytes = (int64_t)op->nelem * ncomp * q * q * q * 8;
     info->map_bytes = (int64_t)op->nelem * d * d * d * 4;

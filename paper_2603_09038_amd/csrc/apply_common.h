@@ -13,7 +13,8 @@
 // input tensors that feed the same output), n over the two untouched indices, and o over
 // the new 1-D index.  The paper's cyclic index order (Sec. III-D) is what makes this
 // uniform: storing each stage's output as [o][n] leaves the next stage's contracted index
-// fastest in memory, so the input of every pass is In[n][k] with unit stride in k.
+// fastest in memory, so the input of every pass is In[n][k] with unit stride in k (and an
+// odd column stride, see the LDS layout below).
 //
 // Two executors consume the same pass descriptors:
 //   * MFMA: v_mfma_f64_4x4x4f64 (four 4x4x4 blocks = a 4x16x4 GEMM slice) with A (the
@@ -60,6 +61,11 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int cmax3(int a, int b, int c) { return cmax(a, cmax(b, c)); }
 constexpr int cclamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+// LDS column stride of a tensor whose fast index has length c: 8-byte reads of 16 lanes
+// (one LDS cycle) at a stride of c doubles fall on gcd(c, 16) times fewer banks than a
+// conflict-free read needs, so strides that are multiples of 4 (4- and 8-way conflicts)
+// are padded by one; the 2-way conflict of c = 2 mod 4 costs less than the footprint.
+__host__ __device__ constexpr int pad_stride(int c) { return c % 4 == 0 ? c + 1 : c; }
 
 // ------------------------------------------------------------------ element-group shape
 // TB: bytes of the LDS/vector scalar type; NT: threads per workgroup; BUDGET: LDS bytes per
@@ -71,17 +77,23 @@ struct Shape {
     static constexpr bool kDiff = (OPS & 2) != 0;
     static constexpr int NCOMP = kDiff ? (kMass ? 7 : 6) : 1;  // stored D values per qp
     static constexpr int NG = kDiff ? (kMass ? 4 : 3) : 1;     // qp channels (grad comps, value)
+    static constexpr int ND = D, NQ = Q;  // 1-D node and quadrature-point counts
     static constexpr int Q3 = Q * Q * Q, D3 = D * D * D;
-    static constexpr int SZ_X = D3;
-    static constexpr int SZ_U1 = (kDiff ? 2 * Q : Q) * D * D;
-    static constexpr int SZ_U2 = (kDiff ? 3 * Q * Q : Q * Q) * D;
-    static constexpr int SZ_G3 = NG * Q3;
-    static constexpr int SZ_W = NG * Q * Q * D;
-    static constexpr int SZ_T = (kDiff ? 2 : 1) * D * D * Q;
+    // element tensors with the fast index stored at stride DP = pad_stride(D) or QP = pad_stride(Q)
+    static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
+    static constexpr int SZ_X = D * D * DP;
+    static constexpr int SZ_U1 = (kDiff ? 2 * Q : Q) * D * DP;
+    static constexpr int SZ_U2 = (kDiff ? 3 * Q * Q : Q * Q) * DP;
+    static constexpr int SZ_G3 = NG * Q * Q * QP;
+    static constexpr int SZ_W = NG * Q * QP * D;
+    static constexpr int SZ_T = (kDiff ? 2 : 1) * D * D * QP;
     // ping-pong LDS regions per element (doubles); odd strides spread elements over banks
     static constexpr int SZ_A = cmax3(SZ_X, SZ_U2, SZ_W) | 1;
     static constexpr int SZ_B = cmax3(SZ_U1, SZ_G3, SZ_T) | 1;
-    static constexpr int SLACK = 16 * 2 * kMaxQ;  // tail of each buffer for padded tile columns
+    // tail of each buffer read by the padding columns of the last element's 16-column tiles
+    // (at most 15 columns past the element region at column stride <= max(DP, QP); the
+    // larger fixed size keeps the measured workgroups-per-CU of every order)
+    static constexpr int SLACK = 16 * 2 * kMaxQ;
     static constexpr int PER_ELEM_BYTES = TB * (SZ_A + SZ_B) + 4 * D3;
     // elements per workgroup from the LDS budget (48 KB -> 3 workgroups per 160 KB CU)
     static constexpr int E = cclamp(BUDGET / PER_ELEM_BYTES, 1, 32);
@@ -123,7 +135,8 @@ __device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassReg
 }
 
 // Store policy of a pass output: into LDS, or atomically / plainly into the global y.
-// `addr` is element-local (OUT + n + NCOL o).
+// `addr` is element-local (OUT + opos(n) + NCOLO o; the last pass writes the natural
+// node order n + D^2 o).
 template <class T>
 struct LdsOut {
     T *out;
@@ -147,6 +160,19 @@ struct GlobalOut {
     }
 };
 
+// LDS layout.  Every per-element tensor is stored with its fast (next-contracted) index
+// at the padded stride DP = pad_stride(D) or QP = pad_stride(Q), so that threads or MFMA
+// lanes reading consecutive columns (column stride CS) spread over the LDS banks.  A pass
+// reads In[n][c] at in_off(t) + n CS + c (c < C) and writes Out[o][n] at
+// OUT + opos(n) + NCOLO o, where opos places the fast part f of n = f + OF s at f + OSTR s:
+// the layout the next pass reads with column stride OSTR.  The last pass writes the
+// element's natural node order (OF = OSTR = NCOL) through the DOF map.
+template <class P>
+struct OutLayout {
+    static constexpr int NCOLO = P::OSTR * (P::NCOL / P::OF);
+    __device__ static int opos(int n) { return P::OF == P::OSTR ? n : (n % P::OF) + P::OSTR * (n / P::OF); }
+};
+
 // Columns are padded to NCOLP (a multiple of 16) per element so that a 16-column tile
 // never straddles two elements: tile t covers element t / TPE, columns
 // n0 = 16 (t % TPE) .. n0 + 15.  Tiles are dealt to the waves round-robin; the tile
@@ -164,8 +190,8 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
                                           const double (&a)[PassRegs<P>::RT][PassRegs<P>::KC],
                                           const Out &out, int wave, int lane)
 {
-    constexpr int C = P::C, K = PassRegs<P>::K, KC = PassRegs<P>::KC, RT = PassRegs<P>::RT;
-    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE, NW = NT / 64;
+    constexpr int C = P::C, CS = P::CS, K = PassRegs<P>::K, KC = PassRegs<P>::KC, RT = PassRegs<P>::RT;
+    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE, NW = NT / 64, NCOLO = OutLayout<P>::NCOLO;
     constexpr int NR = (NTILE + NW - 1) / NW;
     constexpr int BATCH = NR < kMfmaBatch ? NR : kMfmaBatch;
     const int kl = lane >> 4, nl = lane & 15;
@@ -177,9 +203,9 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
         const int k = 4 * kc + kl;
         kval[kc] = k < K;
         const int t = k / C, c = k - t * C;
-        lin[kc] = nl * C + (kval[kc] ? P::in_off(t) + c : 0);
+        lin[kc] = nl * CS + (kval[kc] ? P::in_off(t) + c : 0);
     }
-    const int lout = P::OUT + nl + P::NCOL * kl;
+    const int lout = P::OUT + NCOLO * kl;
 #pragma unroll 1
     for (int r0 = 0; r0 < NR; r0 += BATCH) {
         double bv[BATCH][KC];
@@ -196,7 +222,7 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
             cv[bi] = tv && (n0 + nl < P::NCOL);
             // no masking needed: past K a lane reads a finite value of its own column
             // (A is zero there); padding columns are independent and never stored
-            const double *base = in + e * szin + n0 * C;
+            const double *base = in + e * szin + n0 * CS;
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) bv[bi][kc] = base[lin[kc]];
         }
@@ -215,9 +241,10 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
             if (!cv[bi]) continue;
+            const int ob = lout + OutLayout<P>::opos(n0S[bi] + nl);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
-                if (4 * rt + kl < P::O) out.put(eS[bi], n0S[bi] + lout + 4 * rt * P::NCOL, acc[bi][rt]);
+                if (4 * rt + kl < P::O) out.put(eS[bi], ob + 4 * rt * NCOLO, acc[bi][rt]);
         }
     }
 }
@@ -242,7 +269,7 @@ struct ValuShape {
 template <class P, int E, int NTH, class Out>
 __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevTables *tab, const Out &out, int tid)
 {
-    constexpr int C = P::C, NT = P::NT, O = P::O;
+    constexpr int C = P::C, CS = P::CS, NT = P::NT, O = P::O, NCOLO = OutLayout<P>::NCOLO;
     using V = ValuShape<P, E, NTH>;
     constexpr int NTOT = V::NTOT, OP = V::OP;
     constexpr int NR = (NTOT + NTH - 1) / NTH;
@@ -265,7 +292,7 @@ __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevT
             o0[bi] = part * OP;
             eI[bi] = col / P::NCOL;
             nI[bi] = col - eI[bi] * P::NCOL;
-            const double *base = in + eI[bi] * szin + nI[bi] * C;
+            const double *base = in + eI[bi] * szin + nI[bi] * CS;
 #pragma unroll
             for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -289,9 +316,10 @@ __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevT
                         if (o0[bi] + o < O) acc[o] = fma(P::A(tab, o0[bi] + o, k), xin[bi][k], acc[o]);
             }
             if (cv[bi]) {
+                const int ob = P::OUT + OutLayout<P>::opos(nI[bi]);
 #pragma unroll
                 for (int o = 0; o < OP; ++o)
-                    if (o0[bi] + o < O) out.put(eI[bi], P::OUT + nI[bi] + P::NCOL * (o0[bi] + o), acc[o]);
+                    if (o0[bi] + o < O) out.put(eI[bi], ob + NCOLO * (o0[bi] + o), acc[o]);
             }
         }
     }
@@ -369,8 +397,8 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
                                             const Out &out, int wave, int lane)
 {
     using V = typename Mfma16<BF>::V;
-    constexpr int C = P::C, K = PassRegs16<P>::K, KC = PassRegs16<P>::KC, RB = PassRegs16<P>::RB;
-    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE, NW = NT / 64;
+    constexpr int C = P::C, CS = P::CS, K = PassRegs16<P>::K, KC = PassRegs16<P>::KC, RB = PassRegs16<P>::RB;
+    constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE, NW = NT / 64, NCOLO = OutLayout<P>::NCOLO;
     constexpr int NR = (NTILE + NW - 1) / NW;
     constexpr int BATCH = NR < kMfmaBatch ? NR : kMfmaBatch;
     const int kl = lane >> 4, nl = lane & 15;
@@ -383,9 +411,9 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
             const int k = 16 * kc + 4 * kl + t;
             kval[kc][t] = k < K;
             const int tt = k / C, c = k - tt * C;
-            lin[kc][t] = nl * C + (kval[kc][t] ? P::in_off(tt) + c : 0);
+            lin[kc][t] = nl * CS + (kval[kc][t] ? P::in_off(tt) + c : 0);
         }
-    const int lout = P::OUT + nl + P::NCOL * 4 * kl;
+    const int lout = P::OUT + NCOLO * 4 * kl;
 #pragma unroll 1
     for (int r0 = 0; r0 < NR; r0 += BATCH) {
         V bv[BATCH][KC];
@@ -400,7 +428,7 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
             eS[bi] = e;
             n0S[bi] = n0;
             cv[bi] = tv && (n0 + nl < P::NCOL);
-            const float *base = in + e * szin + n0 * C;
+            const float *base = in + e * szin + n0 * CS;
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
                 float f[4];
@@ -423,12 +451,12 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
             if (!cv[bi]) continue;
+            const int ob = lout + OutLayout<P>::opos(n0S[bi] + nl);
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    if (16 * rb + 4 * kl + v < P::O)
-                        out.put(eS[bi], n0S[bi] + lout + P::NCOL * (16 * rb + v), acc[bi][rb][v]);
+                    if (16 * rb + 4 * kl + v < P::O) out.put(eS[bi], ob + NCOLO * (16 * rb + v), acc[bi][rb][v]);
         }
     }
 }

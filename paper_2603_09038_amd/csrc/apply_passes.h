@@ -21,40 +21,49 @@
 
 namespace hexpa {
 
-// Channel layout of the quadrature-point tensor V (element region of buffer B):
-// dx at 0, dy at Q^3; without the mass term dz at 2Q^3; with it u at 2Q^3 and dz at 3Q^3.
+// Channel layout of the quadrature-point tensor V (element region of buffer B), each
+// channel [c][b][a] with a at stride QP: dx at 0, dy at QP Q^2; without the mass term dz
+// at 2 QP Q^2; with it u at 2 QP Q^2 and dz at 3 QP Q^2.  qpos maps the natural qp index
+// r = a + Q (b + Q c) into a channel.
 template <int Q, bool M>
 struct Chan {
-    static constexpr int Q3 = Q * Q * Q;
-    static constexpr int X = 0, Y = Q3, V = 2 * Q3, Z = (M ? 3 : 2) * Q3;
+    static constexpr int NX = 0, NY = 1, NV = 2, NZ = M ? 3 : 2;  // channel numbers
+    static constexpr int QP = pad_stride(Q), CS = QP * Q * Q;
+    static constexpr int X = NX * CS, Y = NY * CS, V = NV * CS, Z = NZ * CS;
+    __device__ static int qpos(int r) { return r + (QP - Q) * (r / Q); }
 };
 
 // ======================================================================== diffusion
 // Forward x: X[n=(j,k)][i] -> U1[o1][n]: rows o1 < Q are B_x X (BX), rows >= Q are G_x X (GX).
 template <int D, int Q, bool M>
 struct DF1 {
-    static constexpr int NCOL = D * D, C = D, NT = 1, O = 2 * Q, OUT = 0;
+    static constexpr int DP = pad_stride(D);
+    static constexpr int NCOL = D * D, C = D, CS = DP, NT = 1, O = 2 * Q, OUT = 0, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return o < Q ? tB(t, o, k, D) : tG(t, o - Q, k, D); }
 };
 // Forward y on BX: BX[n=(k,a)][j] -> rows o2 < Q: T_BB = B_y BX, rows >= Q: T_BG = G_y BX.
 template <int D, int Q, bool M>
 struct DF2a {
-    static constexpr int NCOL = Q * D, C = D, NT = 1, O = 2 * Q, OUT = 0;
+    static constexpr int DP = pad_stride(D);
+    static constexpr int NCOL = Q * D, C = D, CS = DP, NT = 1, O = 2 * Q, OUT = 0, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return o < Q ? tB(t, o, k, D) : tG(t, o - Q, k, D); }
 };
 // Forward y on GX: T_GB = B_y GX.
 template <int D, int Q, bool M>
 struct DF2b {
-    static constexpr int NCOL = Q * D, C = D, NT = 1, O = Q, OUT = 2 * Q * Q * D;
-    __device__ static constexpr int in_off(int) { return Q * D * D; }
+    static constexpr int DP = pad_stride(D);
+    static constexpr int NCOL = Q * D, C = D, CS = DP, NT = 1, O = Q, OUT = 2 * Q * Q * DP, OF = D, OSTR = DP;
+    __device__ static constexpr int in_off(int) { return Q * D * DP; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
 // Forward z on T_BB[n=(a,b)][k]: dz = G_z T_BB (and u = B_z T_BB, stacked first, with mass).
 template <int D, int Q, bool M>
 struct DF3a {
-    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = M ? 2 * Q : Q, OUT = M ? Chan<Q, M>::V : Chan<Q, M>::Z;
+    static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
+    static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = M ? 2 * Q : Q, OUT = M ? Chan<Q, M>::V : Chan<Q, M>::Z;
+    static constexpr int OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k)
     {
@@ -64,21 +73,24 @@ struct DF3a {
 // Forward z on T_BG: dy = B_z T_BG.
 template <int D, int Q, bool M>
 struct DF3b {
-    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = Q, OUT = Chan<Q, M>::Y;
-    __device__ static constexpr int in_off(int) { return Q * Q * D; }
+    static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
+    static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = Q, OUT = Chan<Q, M>::Y, OF = Q, OSTR = QP;
+    __device__ static constexpr int in_off(int) { return Q * Q * DP; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
 // Forward z on T_GB: dx = B_z T_GB.
 template <int D, int Q, bool M>
 struct DF3c {
-    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = Q, OUT = Chan<Q, M>::X;
-    __device__ static constexpr int in_off(int) { return 2 * Q * Q * D; }
+    static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
+    static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = Q, OUT = Chan<Q, M>::X, OF = Q, OSTR = QP;
+    __device__ static constexpr int in_off(int) { return 2 * Q * Q * DP; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
 // Transposed x of one channel: V_ch[n=(b,c)][a] -> W_slot[i][n] with G^T (dx) or B^T.
 template <int D, int Q, bool M, int CH_OFF, int SLOT, bool GT>
 struct DT1 {
-    static constexpr int NCOL = Q * Q, C = Q, NT = 1, O = D, OUT = SLOT * Q * Q * D;
+    static constexpr int QP = pad_stride(Q);
+    static constexpr int NCOL = Q * Q, C = Q, CS = QP, NT = 1, O = D, OUT = SLOT * Q * QP * D, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return CH_OFF; }
     __device__ static double A(const DevTables *t, int o, int k) { return GT ? tG(t, k, o, D) : tB(t, k, o, D); }
 };
@@ -86,8 +98,9 @@ struct DT1 {
 // Transposed y, path continuing with B_z^T: t1 = B_y^T W0 + G_y^T W1 (+ B_y^T W3).
 template <int D, int Q, bool M>
 struct DT2a {
-    static constexpr int NCOL = Q * D, C = Q, NT = M ? 3 : 2, O = D, OUT = 0;
-    __device__ static constexpr int in_off(int t) { return (t == 2 ? 3 : t) * Q * Q * D; }
+    static constexpr int QP = pad_stride(Q);
+    static constexpr int NCOL = Q * D, C = Q, CS = QP, NT = M ? 3 : 2, O = D, OUT = 0, OF = Q, OSTR = QP;
+    __device__ static constexpr int in_off(int t) { return (t == 2 ? 3 : t) * Q * QP * D; }
     __device__ static double A(const DevTables *tb, int o, int k)
     {
         const int t = k / Q, b = k - t * Q;
@@ -97,15 +110,17 @@ struct DT2a {
 // Transposed y, path continuing with G_z^T: t2 = B_y^T W2.
 template <int D, int Q, bool M>
 struct DT2b {
-    static constexpr int NCOL = Q * D, C = Q, NT = 1, O = D, OUT = D * D * Q;
-    __device__ static constexpr int in_off(int) { return 2 * Q * Q * D; }
+    static constexpr int QP = pad_stride(Q);
+    static constexpr int NCOL = Q * D, C = Q, CS = QP, NT = 1, O = D, OUT = D * D * QP, OF = Q, OSTR = QP;
+    __device__ static constexpr int in_off(int) { return 2 * Q * QP * D; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
 };
 // Transposed z: y_E[k][n=(i,j)] = B_z^T t1 + G_z^T t2 (K-stacked), scattered to y.
 template <int D, int Q, bool M>
 struct DT3 {
-    static constexpr int NCOL = D * D, C = Q, NT = 2, O = D, OUT = 0;
-    __device__ static constexpr int in_off(int t) { return t * Q * D * D; }
+    static constexpr int QP = pad_stride(Q);
+    static constexpr int NCOL = D * D, C = Q, CS = QP, NT = 2, O = D, OUT = 0, OF = NCOL, OSTR = NCOL;
+    __device__ static constexpr int in_off(int t) { return t * D * D * QP; }
     __device__ static double A(const DevTables *tb, int o, int k)
     {
         const int t = k / Q, c = k - t * Q;
@@ -116,37 +131,43 @@ struct DT3 {
 // ======================================================================== mass
 template <int D, int Q>
 struct MF1 {
-    static constexpr int NCOL = D * D, C = D, NT = 1, O = Q, OUT = 0;
+    static constexpr int DP = pad_stride(D);
+    static constexpr int NCOL = D * D, C = D, CS = DP, NT = 1, O = Q, OUT = 0, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
 template <int D, int Q>
 struct MF2 {
-    static constexpr int NCOL = Q * D, C = D, NT = 1, O = Q, OUT = 0;
+    static constexpr int DP = pad_stride(D);
+    static constexpr int NCOL = Q * D, C = D, CS = DP, NT = 1, O = Q, OUT = 0, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
 template <int D, int Q>
 struct MF3 {
-    static constexpr int NCOL = Q * Q, C = D, NT = 1, O = Q, OUT = 0;
+    static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
+    static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = Q, OUT = 0, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
 template <int D, int Q>
 struct MT1 {
-    static constexpr int NCOL = Q * Q, C = Q, NT = 1, O = D, OUT = 0;
+    static constexpr int QP = pad_stride(Q);
+    static constexpr int NCOL = Q * Q, C = Q, CS = QP, NT = 1, O = D, OUT = 0, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
 };
 template <int D, int Q>
 struct MT2 {
-    static constexpr int NCOL = Q * D, C = Q, NT = 1, O = D, OUT = 0;
+    static constexpr int QP = pad_stride(Q);
+    static constexpr int NCOL = Q * D, C = Q, CS = QP, NT = 1, O = D, OUT = 0, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
 };
 template <int D, int Q>
 struct MT3 {
-    static constexpr int NCOL = D * D, C = Q, NT = 1, O = D, OUT = 0;
+    static constexpr int QP = pad_stride(Q);
+    static constexpr int NCOL = D * D, C = Q, CS = QP, NT = 1, O = D, OUT = 0, OF = NCOL, OSTR = NCOL;
     __device__ static constexpr int in_off(int) { return 0; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, k, o, D); }
 };

@@ -63,9 +63,24 @@ struct GroupRegs {
     static constexpr int NM = (S::E * S::D3 + S::THREADS - 1) / S::THREADS;  // map/x slots per thread
 };
 
+// LDS position of local node I = i + D (j + D k) in the padded input X[n=(j,k)][i]
+template <class S>
+__device__ __forceinline__ int xpos(int I)
+{
+    return I + (S::DP - S::ND) * (I / S::ND);
+}
+// LDS position of entry r of the natural quadrature-point tensor [channel][Q^3]
+template <int Q, bool M>
+__device__ __forceinline__ int qtpos(int r)
+{
+    const int ch = r / (Q * Q * Q);
+    return ch * Chan<Q, M>::CS + Chan<Q, M>::qpos(r - ch * Q * Q * Q);
+}
+
 // Workgroup size and LDS budget of the register-staged kernel: diffusion at p <= 4 runs
-// two-wave workgroups of two elements (fewer waves wait at each barrier, more workgroups
-// per CU); everything else four waves and a 48 KB budget (measured per order).
+// two-wave workgroups with a 24 KB element budget (two elements at p = 4; fewer waves wait
+// at each barrier, more workgroups per CU); everything else four waves and a 48 KB budget
+// (measured per order).
 #ifndef HEXPA_SMALL_WG_MAX_D
 #define HEXPA_SMALL_WG_MAX_D 5
 #endif
@@ -73,7 +88,7 @@ template <int D, int OPS, int EX>
 struct ApplyCfg {
     static constexpr bool SMALL = (OPS & 2) != 0 && D <= HEXPA_SMALL_WG_MAX_D && (EX == 0 || EX == 1);
     static constexpr int NT = SMALL ? 128 : kThreads;
-    static constexpr int BUDGET = SMALL ? 20 * 1024 : kLdsBudget;
+    static constexpr int BUDGET = SMALL ? 24 * 1024 : kLdsBudget;
 };
 
 // D of one group into registers: slot s of thread tid is qp entry L = tid + s*THREADS.
@@ -224,7 +239,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
             if (L < E * D3) {
                 const int e = L / D3, I = L - e * D3;
                 lmap[L] = mcur[s];
-                if constexpr (FWD) bufA[e * S::SZ_A + I] = xcur[s];
+                if constexpr (FWD) bufA[e * S::SZ_A + xpos<S>(I)] = xcur[s];
             }
         }
         if constexpr (MF)
@@ -236,7 +251,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         if constexpr (!FWD)  // the quadrature-point tensor, D already applied by k_dstep
             for (int L = tid; L < nv * QT; L += NT) {
                 const int e = L / QT, r = L - e * QT;
-                bufB[e * S::SZ_B + r] = qbuf[(int64_t)(e0 + e) * QT + r];
+                bufB[e * S::SZ_B + qtpos<Q, M>(r)] = qbuf[(int64_t)(e0 + e) * QT + r];
             }
         int32_t mnext[NM];
         load_map<S, EL>(mnext, emap, elist, e0n, nvn, tid);
@@ -276,7 +291,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         if constexpr (STAGE == 1) {  // the quadrature-point tensor goes to HBM; next group
             for (int L = tid; L < nv * QT; L += NT) {
                 const int e = L / QT, r = L - e * QT;
-                qbuf[(int64_t)(e0 + e) * QT + r] = bufB[e * S::SZ_B + r];
+                qbuf[(int64_t)(e0 + e) * QT + r] = bufB[e * S::SZ_B + qtpos<Q, M>(r)];
             }
             if (!more) break;
             lds_barrier();
@@ -296,7 +311,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
             const int L = tid + s * NT;
             if (L < E * Q3) {
                 const int e = L / Q3, r = L - e * Q3;
-                T *V = bufB + e * S::SZ_B + r;
+                T *V = bufB + e * S::SZ_B + Chan<Q, M>::qpos(r);
                 T dmf[MF ? NC : 1];
                 if constexpr (MF) {
                     Hex h;
@@ -385,13 +400,14 @@ __global__ __launch_bounds__(256) void k_dstep(int64_t npts, const T *__restrict
         T *V = qbuf + e * (NG * Q3) + r;
         const T *Dm = qd + e * (NC * Q3) + r;
         if constexpr (S::kDiff) {
-            using CH = Chan<Q, M>;
-            const T g0 = V[CH::X], g1 = V[CH::Y], g2 = V[CH::Z];
+            using CH = Chan<Q, M>;  // channel c of the natural tensor at c Q^3
+            constexpr int X = CH::NX * Q3, Y = CH::NY * Q3, Z = CH::NZ * Q3, U = CH::NV * Q3;
+            const T g0 = V[X], g1 = V[Y], g2 = V[Z];
             const T d0 = Dm[0], d1 = Dm[Q3], d2 = Dm[2 * Q3], d3 = Dm[3 * Q3], d4 = Dm[4 * Q3], d5 = Dm[5 * Q3];
-            V[CH::X] = d0 * g0 + d1 * g1 + d2 * g2;
-            V[CH::Y] = d1 * g0 + d3 * g1 + d4 * g2;
-            V[CH::Z] = d2 * g0 + d4 * g1 + d5 * g2;
-            if constexpr (M) V[CH::V] = Dm[6 * Q3] * V[CH::V];
+            V[X] = d0 * g0 + d1 * g1 + d2 * g2;
+            V[Y] = d1 * g0 + d3 * g1 + d4 * g2;
+            V[Z] = d2 * g0 + d4 * g1 + d5 * g2;
+            if constexpr (M) V[U] = Dm[6 * Q3] * V[U];
         } else {
             V[0] *= Dm[0];
         }
@@ -578,7 +594,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
             T v;
             if constexpr (WIDE) v = __hiloint2double((int)XH[L], (int)XL[L]);
             else v = __uint_as_float(XL[L]);
-            bufA[e * S::SZ_A + I] = v;
+            bufA[e * S::SZ_A + xpos<S>(I)] = v;
         }
         lds_barrier();
         if (more) issue_x(mb1);
@@ -610,7 +626,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
             const int L = tid + s * NT;
             if (L < E * Q3) {
                 const int e = L / Q3, r = L - e * Q3;
-                T *V = bufB + e * S::SZ_B + r;
+                T *V = bufB + e * S::SZ_B + Chan<Q, M>::qpos(r);
                 T dv[NC];
 #pragma unroll
                 for (int c = 0; c < NC; ++c) dv[c] = DREG ? dq[DREG ? s : 0][c] : sD[(e * NC + c) * Q3 + r];
