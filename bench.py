@@ -244,6 +244,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-matrix", action="store_true", help="skip the unfused/fused/matrix-free kernel matrix")
     ap.add_argument("--learned-train", type=int, default=40, help="training draws of the learned preconditioner")
     ap.add_argument("--learned-held", type=int, default=20, help="held-out draws of the learned comparison")
     ap.add_argument("--learned-weights", default=None, help="load parameters from this file instead of training")
@@ -321,9 +322,10 @@ def main():
     qt_bytes = 8 * 3 * q ** 3 * nelem
     matrix = []
     mf_bytes = ab - 8 * 6 * q ** 3 * nelem + nelem * (8 * 4 + 24 * 8)  # no D; hex indices + vertex coordinates
-    for name, v in (("fused_valu", hexpa.PA_VARIANT_VALU), ("fused_mfma", hexpa.PA_VARIANT_MFMA),
-                    ("unfused_valu", hexpa.PA_VARIANT_VALU_UNFUSED), ("unfused_mfma", hexpa.PA_VARIANT_MFMA_UNFUSED),
-                    ("fused_mf_valu", hexpa.PA_VARIANT_VALU_MF), ("fused_mf_mfma", hexpa.PA_VARIANT_MFMA_MF)):
+    variants = (("fused_valu", hexpa.PA_VARIANT_VALU), ("fused_mfma", hexpa.PA_VARIANT_MFMA),
+                ("unfused_valu", hexpa.PA_VARIANT_VALU_UNFUSED), ("unfused_mfma", hexpa.PA_VARIANT_MFMA_UNFUSED),
+                ("fused_mf_valu", hexpa.PA_VARIANT_VALU_MF), ("fused_mf_mfma", hexpa.PA_VARIANT_MFMA_MF))
+    for name, v in (() if args.no_matrix else variants):
         op.set_variant(v)
         km, _ = time_kernel(op, hexpa, x, y, 30, 10)
         hb = ab + 4 * qt_bytes if name.startswith("unfused") else (mf_bytes if "_mf_" in name else ab)
@@ -331,7 +333,8 @@ def main():
                        "hbm_frac_model": hb / (km * 1e-3) / 1e9 / HBM_PEAK_GBS})
         log(f"kernel matrix {name}: {km:.4f} ms")
     op.set_variant(VAR[used])
-    out["kernel_matrix"] = matrix
+    if matrix:
+        out["kernel_matrix"] = matrix
     if not args.no_cg:
         out["cg"] = run_cg(hexpa, mesh, coeff, p, q)
         log(f"C2 Jacobi-PCG: {out['cg']['iters']} iterations, {out['cg']['seconds']:.3f} s")

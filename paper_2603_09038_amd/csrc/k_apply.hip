@@ -469,7 +469,10 @@ struct DmaShape {
     static constexpr bool DREG = HEXPA_APPLY_DMA == 2;
     static constexpr int PER = TB * (B::SZ_A + B::SZ_B) + 12 * B::D3 + (TB == 8 ? 8 : 4) * B::D3 +
                                (DREG ? 0 : TB * B::NCOMP * B::Q3);
-    static constexpr int FIXED = TB * 2 * B::SLACK + (int)sizeof(DevTables);
+    // buffer tails for the padding columns of 16-column tiles (the exact bound; the smaller
+    // footprint keeps four workgroups per CU for the 16-bit apply at p = 6)
+    static constexpr int SLACK = 16 * cmax(B::DP, B::QP);
+    static constexpr int FIXED = TB * 2 * SLACK + (int)sizeof(DevTables);
     static constexpr int E = cclamp((HEXPA_DMA_LDS_BUDGET - FIXED) / PER, 1, 32);
     static constexpr bool ok = HEXPA_APPLY_DMA != 0 && D >= HEXPA_DMA_MIN_D &&
                                (DREG || (E >= 2 && (B::NCOMP * B::Q3 * TB) % 16 == 0));
@@ -492,8 +495,8 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
     constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
     __shared__ T sD[DREG ? 1 : E * NC * Q3];
     T dq[DREG ? NSD : 1][NC];
-    __shared__ T bufA[E * S::SZ_A + S::SLACK];
-    __shared__ T bufB[E * S::SZ_B + S::SLACK];
+    __shared__ T bufA[E * S::SZ_A + DmaShape<D, Q, OPS, T>::SLACK];
+    __shared__ T bufB[E * S::SZ_B + DmaShape<D, Q, OPS, T>::SLACK];
     __shared__ int32_t mapb[3][ED3];
     __shared__ uint32_t XL[ED3], XH[WIDE ? ED3 : 1];
     __shared__ DevTables stab;
