@@ -164,6 +164,18 @@ def run_mixed(hexpa, n=32, p=6, q=8):
         x = torch.zeros_like(b)
         hexpa.cg_solve(op.h, b, x, rtol=1e-2, max_it=1, mode=hexpa.PA_CG_MIXED_IR, lp_fmt=fmt, inner_max=5,
                        raise_on_fail=False)
+    # normwise error of the 16-bit apply against the FP64 apply (unconstrained operator) for
+    # a rough input (x ~ U[-1,1]) and a smooth one (the manufactured x*): rounding the
+    # interpolated tile before differentiating costs more, relative to |A x|, when A x is small
+    xr = torch.tensor(synth.rand_x(op.ndof, 1), device="cuda")
+    lp_err = {}
+    for xname, xin in (("rough", xr), ("smooth", xs)):
+        ref = op.apply(xin)
+        for name, fmt in (("fp16", hexpa.PA_LP_FP16), ("bf16", hexpa.PA_LP_BF16)):
+            y16 = op.apply_lp(xin.float(), fmt=fmt).double()
+            lp_err[f"{name}_{xname}"] = float(torch.linalg.norm(y16 - ref) / torch.linalg.norm(ref))
+    out["lp_apply_rel_err"] = lp_err
+    log(f"16-bit apply error vs FP64: {lp_err}")
     for tol in (1e-8, 1e-10):
         x = torch.zeros_like(b)
         r = hexpa.cg_solve(op.h, b, x, rtol=tol, max_it=50000, mode=hexpa.PA_CG_JACOBI, check_every=8,
