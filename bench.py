@@ -100,6 +100,96 @@ def time_kernel(op, hexpa, x, y, steps, warmup):
     return float(np.mean(kern)), float(np.median(kern))
 
 
+def energy_per_dof(op, hexpa, x, y, ndof, seconds=3.0):
+    """Throughput per watt of sustained applies (the paper's MDOF/W, Table VI): the socket
+    power the driver reports, sampled every 20 ms while batches of applies run back to back
+    (the first 0.5 s, while clocks and power settle, are dropped).  Returns None with the
+    reason when the power readout is not available."""
+    import torch
+    try:
+        import amdsmi
+    except Exception as e:  # noqa: BLE001
+        return {"error": f"amdsmi not importable: {e}"}
+    try:
+        amdsmi.amdsmi_init()
+    except Exception as e:  # noqa: BLE001
+        return {"error": f"amdsmi_init failed: {e}"}
+    try:
+        handles = amdsmi.amdsmi_get_processor_handles()
+        h = handles[0] if len(handles) == 1 else None
+        try:
+            bus = torch.cuda.get_device_properties(0).pci_bus_id
+            for hh in handles:
+                bdf = amdsmi.amdsmi_get_gpu_device_bdf(hh)
+                if int(bdf.split(":")[1], 16) == bus:
+                    h = hh
+        except Exception:  # noqa: BLE001
+            pass
+        if h is None:
+            return {"error": f"cannot tell which of {len(handles)} devices runs the applies"}
+
+        def watts():
+            info = amdsmi.amdsmi_get_power_info(h)
+            for key in ("current_socket_power", "average_socket_power"):
+                v = info.get(key)
+                if isinstance(v, (int, float)) and v > 0:
+                    return float(v), key
+            return None, None
+
+        if watts()[0] is None:
+            return {"error": "no socket power reading"}
+        samples, key = [], None
+        batch = 100
+
+        def enqueue():
+            for _ in range(batch):
+                hexpa.pa_apply(op.h, x, y)
+            ev = torch.cuda.Event()
+            ev.record()
+            return ev
+
+        # two batches in flight, so the device never waits for the host between batches
+        for _ in range(3):
+            enqueue()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pending = enqueue()
+        n_done, t_start, t_end = 0, None, None
+        while True:
+            nxt = enqueue() if time.perf_counter() - t0 < seconds else None
+            while not pending.query():
+                time.sleep(0.02)
+                w, key = watts()
+                if t_start is not None and w is not None:
+                    samples.append(w)
+            now = time.perf_counter()
+            if t_start is None:
+                if now - t0 >= 0.5:
+                    t_start = now  # the batches completing after this point are counted
+            else:
+                n_done += batch
+                t_end = now
+            if nxt is None:
+                break
+            pending = nxt
+        torch.cuda.synchronize()
+        if t_start is None or not samples or n_done == 0:
+            return {"error": "window too short"}
+        dt = t_end - t_start
+        w = float(np.mean(samples))
+        rate = n_done * ndof / dt
+        return {"watts_mean": w, "watts_min": float(np.min(samples)), "watts_max": float(np.max(samples)),
+                "samples": len(samples), "source": f"amdsmi {key}", "applies": n_done, "seconds": dt,
+                "gdofs": rate / 1e9, "mdof_per_watt": rate / 1e6 / w}
+    except Exception as e:  # noqa: BLE001
+        return {"error": f"{type(e).__name__}: {e}"}
+    finally:
+        try:
+            amdsmi.amdsmi_shut_down()
+        except Exception:  # noqa: BLE001
+            pass
+
+
 def cpu_baseline(mesh, p, q, coeff_o, ops_o, ndof, nelem, budget_s):
     import oracle
     P = oracle.Problem(mesh, p, q, coeff=coeff_o, ops=ops_o)
@@ -250,13 +340,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    # 200 untimed applies (~70 ms) let the clocks reach their sustained level first
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--variant", default="auto", choices=["auto", "mfma", "valu", "colored"])
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle CPU work (0 = skip)")
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-matrix", action="store_true", help="skip the unfused/fused/matrix-free kernel matrix")
+    ap.add_argument("--no-energy", action="store_true", help="skip the MDOF/W measurement")
     ap.add_argument("--learned-train", type=int, default=40, help="training draws of the learned preconditioner")
     ap.add_argument("--learned-held", type=int, default=20, help="held-out draws of the learned comparison")
     ap.add_argument("--learned-weights", default=None, help="load parameters from this file instead of training")
@@ -265,8 +357,7 @@ def main():
     ap.add_argument("--sweep", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -347,6 +438,9 @@ def main():
     op.set_variant(VAR[used])
     if matrix:
         out["kernel_matrix"] = matrix
+    if not args.no_energy:
+        out["energy"] = energy_per_dof(op, hexpa, x, y, ndof)
+        log(f"energy: {out['energy']}")
     if not args.no_cg:
         out["cg"] = run_cg(hexpa, mesh, coeff, p, q)
         log(f"C2 Jacobi-PCG: {out['cg']['iters']} iterations, {out['cg']['seconds']:.3f} s")

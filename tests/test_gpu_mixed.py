@@ -4,7 +4,8 @@ Bars.  The 16-bit apply is not expected to match the FP64 oracle to rounding: ev
 element tile and intermediate tensor is rounded to FP16 (unit roundoff u = 2^-11) or BF16
 (u = 2^-8) before it enters an MFMA.  Six roundings along the contraction chain with
 FP32 accumulation give a normwise relative error of a few u for rough inputs; the bounds
-below are 8u (FP16: 3.9e-3) and 8u (BF16: 3.1e-2), stated in the design doc.  The solver is
+below are 8u (FP16: 3.9e-3) and 8u (BF16: 3.1e-2): real indexing or scaling errors show
+at O(1), rounding stays a small multiple of u.  The solver is
 judged in FP64: its true residual, recomputed by the CPU oracle's operator, must meet the
 requested 1e-10.
 """
