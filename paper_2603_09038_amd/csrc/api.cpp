@@ -969,6 +969,9 @@ extern "C" int cg_solve(pa_op *op, const double *b, double *x, const pa_cg_opts 
     if (o->mode != PA_CG_PLAIN && o->mode != PA_CG_JACOBI && o->mode != PA_CG_MIXED_IR && o->mode != PA_CG_FCG &&
         o->mode != PA_CG_MIXED_FCG && o->mode != PA_CG_MIXED_RU)
         return arg_error("cg_solve: unknown mode");
+    if (o->mode == PA_CG_FCG && !o->lp) return arg_error("cg_solve: PA_CG_FCG needs opts->lp");
+    if (o->mode == PA_CG_FCG && lp_operator(o->lp) != op)
+        return arg_error("cg_solve: the pa_lp handle is bound to another operator");
     if (o->n_capture < 0 ||
         (o->n_capture > 0 && ((o->mode != PA_CG_JACOBI && o->mode != PA_CG_FCG) || !o->capture_at || !o->capture_x)))
         return arg_error("cg_solve: capture needs PA_CG_JACOBI or PA_CG_FCG, capture_at and capture_x");

@@ -57,6 +57,11 @@ def test_bad_arguments_are_rejected_without_a_device(lib):
     assert lib.pa_setup(ctypes.byref(md), 2, 4, None, 0, None, ctypes.byref(h)) == hexpa.PA_ERR_ARG
     md.nx = 2
     assert lib.pa_setup(ctypes.byref(md), 2, 4, None, 2, None, ctypes.byref(h)) == hexpa.PA_ERR_ARG
+    md.nx = 1
+    md.nelem = 0  # an empty mesh is rejected, not silently accepted
+    assert lib.pa_setup(ctypes.byref(md), 2, 4, None, 2, None, ctypes.byref(h)) == hexpa.PA_ERR_ARG
+    md.nelem, md.nvert = 1, 0
+    assert lib.pa_setup(ctypes.byref(md), 2, 4, None, 2, None, ctypes.byref(h)) == hexpa.PA_ERR_ARG
     assert lib.pa_apply(None, None, None, None) == hexpa.PA_ERR_ARG
     assert lib.pa_diag(None, None, 0, None) == hexpa.PA_ERR_ARG
     assert lib.cg_solve(None, None, None, None, None, None) == hexpa.PA_ERR_ARG

@@ -294,3 +294,31 @@ def test_full_size_mixed_workload_lp_apply_sampled_rows(hx):
         y = op.apply_lp(x32, fmt=fmt).double().cpu().numpy()
         assert np.abs(y[rows] - ref).max() <= 16 * u * scale, (fmt, np.abs(y[rows] - ref).max() / scale)
     op.close()
+
+
+def test_zero_input_and_zero_right_hand_side(hx):
+    """Degenerate inputs: A 0 = 0 exactly for every variant; b = 0 returns x = 0 exactly, with
+    no iteration, for every solver mode (a nonzero initial guess is overwritten); FCG without
+    a preconditioner handle is still rejected."""
+    import torch
+    mesh = synth.box_mesh(3, perturb=0.1, seed=4)
+    for ops in (1, 2, 3):
+        op = hx.PAOperator(mesh, 2, 4, ops=ops, ess_mode=1)
+        z = torch.zeros(op.ndof, dtype=torch.float64, device="cuda")
+        for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU, hx.PA_VARIANT_MFMA_COLORED,
+                        hx.PA_VARIANT_MFMA_UNFUSED, hx.PA_VARIANT_VALU_UNFUSED, hx.PA_VARIANT_MFMA_MF,
+                        hx.PA_VARIANT_VALU_MF):
+            op.set_variant(variant)
+            y = op.apply(z)
+            assert torch.count_nonzero(y).item() == 0, (ops, variant)
+        op.set_variant(hx.PA_VARIANT_MFMA)
+        if ops == 2:
+            for mode in (hx.PA_CG_PLAIN, hx.PA_CG_JACOBI, hx.PA_CG_MIXED_IR, hx.PA_CG_MIXED_FCG, hx.PA_CG_MIXED_RU):
+                x = _cuda(synth.rand_x(op.ndof, 1))
+                r = hx.cg_solve(op.h, z, x, rtol=1e-8, max_it=50, mode=mode)
+                assert r["rc"] == 0 and r["iters"] == 0, (mode, r)
+                assert torch.count_nonzero(x).item() == 0, mode
+            x = torch.zeros_like(z)
+            r = hx.cg_solve(op.h, z, x, mode=hx.PA_CG_FCG, raise_on_fail=False)
+            assert r["rc"] == hx.PA_ERR_ARG
+        op.close()
