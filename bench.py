@@ -287,17 +287,18 @@ def run_mixed(hexpa, n=32, p=6, q=8):
                             "status": r["rc"]}
                 out[f"speedup_{outer}_{name}_{tol:.0e}"] = out[f"fp64_pcg_{tol:.0e}"]["seconds"] / r["seconds"]
         # one FP32 recurrence with reliable updates (FP64 residual replacement at most every
-        # RU_PERIOD iterations); FP16 only: BF16's operator error makes the recursion drift
-        # too fast for this scheme (measured 3-10x more iterations)
-        x = torch.zeros_like(b)
-        r = hexpa.cg_solve(op.h, b, x, rtol=tol, max_it=20000, mode=hexpa.PA_CG_MIXED_RU, lp_fmt=hexpa.PA_LP_FP16,
-                           inner_max=RU_PERIOD, raise_on_fail=False)
-        err = float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs))
-        out[f"mixed_ru_fp16_{tol:.0e}"] = {"seconds": r["seconds"], "replacements": r["iters"],
-                                           "iters": r["inner_iters_total"], "period_max": RU_PERIOD,
-                                           "rel_res_true": r["rel_res_true"], "rel_err_vs_xstar": err,
-                                           "status": r["rc"]}
-        out[f"speedup_ru_fp16_{tol:.0e}"] = out[f"fp64_pcg_{tol:.0e}"]["seconds"] / r["seconds"]
+        # RU_PERIOD iterations), with the FP16 apply and with the BF16 apply (whose element
+        # tiles are centred on their means before rounding)
+        for name, fmt in (("fp16", hexpa.PA_LP_FP16), ("bf16", hexpa.PA_LP_BF16)):
+            x = torch.zeros_like(b)
+            r = hexpa.cg_solve(op.h, b, x, rtol=tol, max_it=20000, mode=hexpa.PA_CG_MIXED_RU, lp_fmt=fmt,
+                               inner_max=RU_PERIOD, raise_on_fail=False)
+            err = float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs))
+            out[f"mixed_ru_{name}_{tol:.0e}"] = {"seconds": r["seconds"], "replacements": r["iters"],
+                                                 "iters": r["inner_iters_total"], "period_max": RU_PERIOD,
+                                                 "rel_res_true": r["rel_res_true"], "rel_err_vs_xstar": err,
+                                                 "status": r["rc"]}
+            out[f"speedup_ru_{name}_{tol:.0e}"] = out[f"fp64_pcg_{tol:.0e}"]["seconds"] / r["seconds"]
     op.close()
     return out
 

@@ -29,6 +29,9 @@
 #ifndef HEXPA_LDS_BARRIER
 #define HEXPA_LDS_BARRIER 1
 #endif
+#ifndef HEXPA_LP_CENTRE
+#define HEXPA_LP_CENTRE 1
+#endif
 
 namespace hexpa {
 
@@ -69,6 +72,33 @@ __device__ __forceinline__ int xpos(int I)
 {
     return I + (S::DP - S::ND) * (I / S::ND);
 }
+// Centre every staged x tile on its element mean (the BF16 diffusion apply).  Diffusion
+// annihilates constants element by element (the reference gradients of the basis sum to
+// zero), so y_E is unchanged in exact arithmetic, while the 16-bit rounding of the tile at
+// the MFMA input now acts on the deviation from the mean instead of the full values: for a
+// smooth x this removes the error term proportional to u |mean| (at the 32^3, p = 6 mixed
+// workload: 16x smaller error for a smooth x in BF16, 10x in FP16).  One wave per element
+// forms the mean (FP32, fixed order); two LDS barriers, ~7 % of the apply.  FP16 keeps the
+// plain tile: its reliable-update solve was no faster with centring.
+template <class S, int E, int NT, class T>
+__device__ __forceinline__ void centre_tiles(T *bufA, T *emean, int tid)
+{
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int e = wave; e < E; e += NT / 64) {
+        T sum = T(0);
+        for (int I = lane; I < S::D3; I += 64) sum += bufA[e * S::SZ_A + xpos<S>(I)];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if (lane == 0) emean[e] = sum / T(S::D3);
+    }
+    lds_barrier();
+    for (int L = tid; L < E * S::D3; L += NT) {
+        const int e = L / S::D3, I = L - e * S::D3;
+        bufA[e * S::SZ_A + xpos<S>(I)] -= emean[e];
+    }
+    lds_barrier();
+}
+
 // LDS position of entry r of the natural quadrature-point tensor [channel][Q^3]
 template <int Q, bool M>
 __device__ __forceinline__ int qtpos(int r)
@@ -190,6 +220,8 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     __shared__ T bufB[E * S::SZ_B + S::SLACK];
     __shared__ int32_t lmap[E * D3];
     __shared__ DevTables stab;  // 1-D tables in LDS: MFMA A-operands are re-read per pass
+    constexpr bool CENTRE = HEXPA_LP_CENTRE && EX == EX_MFMA16B && OPS == 2;
+    __shared__ T emean[CENTRE ? E : 1];
 
     const int tid = threadIdx.x;
     for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
@@ -258,6 +290,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         T dnext[kPrefetchD ? NS : 1][NC];
         if constexpr (kPrefetchD) load_qdata<S, EL>(dnext, qd, elist, e0n, nvn, tid);
         lds_barrier();
+        if constexpr (CENTRE && FWD) centre_tiles<S, E, NT>(bufA, emean, tid);
 
         // forward contractions
         if constexpr (!FWD) {
@@ -500,6 +533,8 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
     __shared__ int32_t mapb[3][ED3];
     __shared__ uint32_t XL[ED3], XH[WIDE ? ED3 : 1];
     __shared__ DevTables stab;
+    constexpr bool CENTRE = HEXPA_LP_CENTRE && EX == EX_MFMA16B && OPS == 2;
+    __shared__ T emean[CENTRE ? E : 1];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -602,6 +637,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
         lds_barrier();
         if (more) issue_x(mb1);
         if (more2) issue_map(gn2, mb2);
+        if constexpr (CENTRE) centre_tiles<S, E, NT>(bufA, emean, tid);
 
         // forward contractions
         if constexpr (S::kDiff) {

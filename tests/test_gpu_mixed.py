@@ -89,7 +89,27 @@ def test_lp_apply_accuracy(hx, p, ops, fmt):
     op.close()
 
 
-@pytest.mark.parametrize("outer,fmt", [("ir", 0), ("ir", 1), ("fcg", 0), ("fcg", 1), ("ru", 0)])
+@pytest.mark.parametrize("p", [4, 6])
+def test_bf16_diffusion_apply_ignores_constants(hx, p):
+    """The BF16 diffusion apply centres every element tile on its mean before rounding
+    (diffusion annihilates constants element by element), so adding a constant to x changes
+    the result only through FP32 rounding of the shifted input; an uncentred BF16 tile would
+    carry an error of about u_bf16 times the constant (here O(1) relative)."""
+    import torch
+    n = {4: 3, 6: 2}[p]  # register-staged kernel at p = 4, direct-to-LDS kernel at p = 6
+    mesh = synth.box_mesh(n, perturb=0.1, seed=p)
+    op = hx.PAOperator(mesh, p, p + 2, ops=hx.PA_DIFFUSION)
+    x = synth.rand_x(op.ndof, 3)
+    y0 = op.apply_lp(_t(x, torch.float32), fmt=1).double().cpu().numpy()
+    y1 = op.apply_lp(_t(x + 64.0, torch.float32), fmt=1).double().cpu().numpy()
+    rel = np.linalg.norm(y1 - y0) / np.linalg.norm(y0)
+    assert rel <= 1e-2, (p, rel)
+    ref = oracle.Problem(mesh, p, p + 2, ops=oracle.DIFFUSION).apply(x)
+    assert np.linalg.norm(y1 - ref) / np.linalg.norm(ref) <= 8 * 2.0 ** -8
+    op.close()
+
+
+@pytest.mark.parametrize("outer,fmt", [("ir", 0), ("ir", 1), ("fcg", 0), ("fcg", 1), ("ru", 0), ("ru", 1)])
 def test_mixed_ir_reaches_fp64_tolerance(hx, fmt, outer):
     """Log-normal coefficient (sigma = 1, correlation length 0.1), p = 6, Q = 8, Dirichlet,
     b = A_c x* with x* the nodal interpolant of sin(pi x) sin(pi y) sin(pi z)."""
