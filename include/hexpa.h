@@ -79,7 +79,8 @@ typedef struct {
 } pa_coeff_desc;
 
 /* Apply-kernel variants (pa_set_variant).  pa_setup selects the faster contraction unit
-   measured on MI355X for the order: VALU for p <= 4, MFMA for p >= 5. */
+   measured on MI355X for the order and operator: VALU for p <= 4 and for the mass operator
+   alone up to p = 6, MFMA otherwise. */
 #define PA_VARIANT_MFMA 0    /* fused kernel, FP64 MFMA contractions, atomic scatter */
 #define PA_VARIANT_VALU 1    /* fused kernel, FP64 vector-ALU contractions, atomic scatter */
 #define PA_VARIANT_MFMA_COLORED 2 /* MFMA contractions, 8 colour launches, plain read-modify-write

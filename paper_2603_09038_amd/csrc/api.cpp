@@ -115,8 +115,9 @@ extern "C" int pa_setup(const pa_mesh_desc *m, int order, int q1d, const pa_coef
 
     std::unique_ptr<pa_op, void (*)(pa_op *)> op(new pa_op, pa_destroy);
     op->p = order; op->d = order + 1; op->q = q1d; op->ops = (int)ops;
-    // default contraction unit: the faster one measured on MI355X for this order
-    op->variant = order <= 4 ? PA_VARIANT_VALU : PA_VARIANT_MFMA;
+    // default contraction unit: the faster one measured on MI355X for this order and operator
+    // (vector ALU up to p = 4, and for the mass operator alone up to p = 6; MFMA above)
+    op->variant = (order <= 4 || (ops == PA_MASS && order <= 6)) ? PA_VARIANT_VALU : PA_VARIANT_MFMA;
     op->ncomp = (ops & PA_DIFFUSION) ? ((ops & PA_MASS) ? 7 : 6) : 1;
     op->nelem = m->nelem; op->nvert = m->nvert;
     std::string terr;
