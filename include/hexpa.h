@@ -128,8 +128,10 @@ int pa_apply_add(pa_op *op, const double *x, double *y, void *stream);
    of D (rounded once from FP64, made on first use); the element tiles and every
    intermediate of the sum-factorised contractions are rounded to FP16 (fmt = PA_LP_FP16)
    or BF16 (PA_LP_BF16) as they enter v_mfma_f32_16x16x16{f16,bf16}, which accumulates in
-   FP32.  FP16 needs |x| well inside its range: callers scale x by a power of two.
-   y is overwritten.  Asynchronous. */
+   FP32.  For the diffusion operator alone in BF16, each element tile is first centred on
+   its mean (diffusion annihilates constants, so y is unchanged in exact arithmetic and the
+   rounding acts on the deviation from the mean).  FP16 needs |x| well inside its range:
+   callers scale x by a power of two.  y is overwritten.  Asynchronous. */
 #define PA_LP_FP16 0
 #define PA_LP_BF16 1
 int pa_apply_lp(pa_op *op, const float *x, float *y, int fmt, void *stream);
