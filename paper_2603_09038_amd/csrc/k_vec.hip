@@ -7,6 +7,10 @@
 
 namespace hexpa {
 
+// Grid-stride loops of the CG vector kernels keep kUnroll strides of loads in flight per
+// thread (the order of every per-thread sum is unchanged).
+constexpr int kUnroll = 4;
+
 namespace {
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -55,8 +59,19 @@ __global__ void k_dot_partial(const T *__restrict__ x, const T *__restrict__ y, 
 {
     __shared__ double sh[256];
     double v[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        v[0] = fma((double)x[i], (double)y[i], v[0]);
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kUnroll - 1) * st < n; i += kUnroll * st) {  // loads of kUnroll strides in flight
+        T xv[kUnroll], yv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            xv[u] = x[i + u * st];
+            yv[u] = y[i + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) v[0] = fma((double)xv[u], (double)yv[u], v[0]);
+    }
+    for (; i < n; i += st) v[0] = fma((double)x[i], (double)y[i], v[0]);
     block_sum<1>(v, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
 }
@@ -141,14 +156,31 @@ __global__ void k_cg_update1(T *__restrict__ x, T *__restrict__ r, const T *__re
     }
     __syncthreads();  // sh is reused below
     double v[2] = {0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        x[i] = (T)fma(alpha, (double)p[i], (double)x[i]);
-        const T ri = (T)fma(-alpha, (double)Ap[i], (double)r[i]);
+    auto one = [&](int64_t i, T pi, T xi, T ai, T r0, T di) {
+        x[i] = (T)fma(alpha, (double)pi, (double)xi);
+        const T ri = (T)fma(-alpha, (double)ai, (double)r0);
         r[i] = ri;
-        const double zi = dinv ? (double)(dinv[i] * ri) : (double)ri;
+        const double zi = dinv ? (double)(di * ri) : (double)ri;
         v[0] = fma((double)ri, zi, v[0]);
         v[1] = fma((double)ri, (double)ri, v[1]);
+    };
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kUnroll - 1) * st < n; i += kUnroll * st) {  // same order, loads batched
+        T pv[kUnroll], xv[kUnroll], av[kUnroll], rv[kUnroll], dv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t j = i + u * st;
+            pv[u] = p[j];
+            xv[u] = x[j];
+            av[u] = Ap[j];
+            rv[u] = r[j];
+            dv[u] = dinv ? dinv[j] : T(1);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) one(i + u * st, pv[u], xv[u], av[u], rv[u], dv[u]);
     }
+    for (; i < n; i += st) one(i, p[i], x[i], Ap[i], r[i], dinv ? dinv[i] : T(1));
     block_sum<2>(v, sh);
     if (threadIdx.x == 0) {
         rz_part[2 * blockIdx.x] = v[0];
@@ -183,7 +215,26 @@ __global__ void k_cg_update2(T *__restrict__ p, const T *__restrict__ r, const T
         rr_hist[2 * it] = v[1];
         rr_hist[2 * it + 1] = (double)s->breakdown;
     }
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kUnroll - 1) * st < n; i += kUnroll * st) {  // loads batched
+        T rv[kUnroll], dv[kUnroll], pv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t j = i + u * st;
+            rv[u] = r[j];
+            dv[u] = dinv ? dinv[j] : T(1);
+            pv[u] = p[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t j = i + u * st;
+            const double zi = dinv ? (double)(dv[u] * rv[u]) : (double)rv[u];
+            p[j] = (T)fma(beta, (double)pv[u], zi);
+            if (Ap_zero) Ap_zero[j] = T(0);
+        }
+    }
+    for (; i < n; i += st) {
         const double zi = dinv ? (double)(dinv[i] * r[i]) : (double)r[i];
         p[i] = (T)fma(beta, (double)p[i], zi);
         if (Ap_zero) Ap_zero[i] = T(0);
