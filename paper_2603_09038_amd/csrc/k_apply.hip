@@ -229,11 +229,14 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
 
     // Workgroup b runs on XCD b % 8.  XCD x owns the contiguous group range
     // [G x / 8, G (x+1) / 8) so neighbouring elements (sharing DOFs of x and y) meet in the
-    // same L2; its workgroups take that range's groups round-robin.
+    // same L2; its workgroups take that range's groups round-robin.  The two-wave diffusion
+    // instances instead stride over all groups in launch order (neighbouring groups on
+    // different XCDs), measured 4-5 % faster for them at p = 2..4; the four-wave instances
+    // keep the XCD ranges (p = 4 mass 2.5 % faster with them).
     // (Grids of fewer than 8 workgroups just stride over all groups.)
     const int nb = gridDim.x;
     int g, gend, nbx;
-    if (nb >= 8) {
+    if (!CFG::SMALL && nb >= 8) {
         const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
         nbx = (nb >> 3) + (xcd < (nb & 7) ? 1 : 0);
         gend = (int)(((int64_t)ngroups * (xcd + 1)) >> 3);
