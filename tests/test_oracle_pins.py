@@ -25,6 +25,34 @@ def test_gll_closed_forms():
     np.testing.assert_allclose(oracle.gll(4), [0.0, (1 - s) / 2, 0.5, (1 + s) / 2, 1.0], atol=1e-15)
 
 
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6, 7, 8])
+def test_gll_roots_and_lobatto_exactness(p):
+    """GLL nodes at every order the library instantiates, pinned two ways that share nothing
+    with the oracle's bisection: (i) the interior nodes are the roots of P_p' as numpy's
+    Legendre class finds them (companion-matrix eigenvalues); (ii) the interpolatory rule
+    on the nodes (weights = integrals of the Lagrange basis on the nodes) is
+    exact for x^k, k <= 2p - 1, the property that singles out the Lobatto points among
+    (p+1)-point rules through both endpoints, and at degree 2p its error is the Lobatto
+    remainder -n (n-1)^3 2^(2n-1) ((n-2)!)^4 / ((2n-1) ((2n-2)!)^3) f^(2n-2) on [-1,1]
+    (n = p + 1 points), mapped to [0,1]."""
+    from math import factorial
+    x = oracle.gll(p)
+    t = np.sort(np.polynomial.legendre.Legendre.basis(p).deriv().roots().real)
+    np.testing.assert_allclose(x[1:-1], (t + 1) / 2, atol=1e-13)
+    # w_i = integral of l_i: the product formula at numpy's Gauss points (exact for degree p)
+    tg, wg = np.polynomial.legendre.leggauss(p + 1)
+    tg, wg = (tg + 1) / 2, wg / 2
+    w = np.array([wg @ np.prod([(tg - x[j]) / (x[i] - x[j]) for j in range(p + 1) if j != i], axis=0)
+                  for i in range(p + 1)])
+    for k in range(2 * p):
+        assert abs(w @ x ** k - 1 / (k + 1)) < 1e-13, (p, k)
+    n = p + 1
+    e11 = -n * (n - 1) ** 3 * 2.0 ** (2 * n - 1) * factorial(n - 2) ** 4 / ((2 * n - 1) * factorial(2 * n - 2) ** 3)
+    rem = 0.5 * e11 * factorial(2 * p) / 2.0 ** (2 * p)  # f = x^(2p) on [0,1]
+    err = 1 / (2 * p + 1) - w @ x ** (2 * p)
+    assert abs(err - rem) <= 1e-6 * abs(rem), (p, err, rem)
+
+
 def test_gauss_closed_forms():
     x, w = oracle.gauss(2)
     s = 1 / np.sqrt(3)
@@ -315,6 +343,27 @@ def test_diffusion_sheared_affine():
             exact = np.sum(wts * np.sum(grad_mono(e1, xs) * grad_mono(e2, xs), axis=1))
             assert abs(v @ Ku - exact) < 1e-11 * max(1.0, abs(exact)), (e1, e2)
     del Linv
+
+
+@pytest.mark.parametrize("p", [2, 5])
+def test_mass_plus_diffusion_is_the_sum(p):
+    """ops = MASS | DIFFUSION assembles both terms in one pass over the quadrature points;
+    it must equal the mass result plus the diffusion result (a dropped or doubled term in
+    the combined path fails), element matrices and global apply alike, on a perturbed mesh
+    with a variable coefficient."""
+    m = synth.box_mesh(2, perturb=0.1, seed=6)
+    c = oracle.Coeff.sine()
+    Pm = oracle.Problem(m, p, p + 2, coeff=c, ops=oracle.MASS)
+    Pk = oracle.Problem(m, p, p + 2, coeff=c, ops=oracle.DIFFUSION)
+    Pb = oracle.Problem(m, p, p + 2, coeff=c, ops=oracle.MASS | oracle.DIFFUSION)
+    Am, Ak, Ab = Pm.elem_matrices(), Pk.elem_matrices(), Pb.elem_matrices()
+    assert np.abs(Ab - (Am + Ak)).max() <= 1e-14 * np.abs(Ab).max()
+    # both parts are present with their own size: neither is negligible against the other
+    assert np.abs(Am).max() > 1e-3 * np.abs(Ak).max()
+    x = synth.rand_x(Pb.ndof, 3)
+    yb, ym, yk = Pb.apply(x), Pm.apply(x), Pk.apply(x)
+    assert np.linalg.norm(yb - ym - yk) <= 1e-14 * np.linalg.norm(yb)
+    np.testing.assert_allclose(Pb.diag(), Pm.diag() + Pk.diag(), rtol=1e-14, atol=0)
 
 
 @pytest.mark.parametrize("ops", [oracle.MASS, oracle.DIFFUSION, oracle.MASS | oracle.DIFFUSION])
