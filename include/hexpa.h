@@ -98,7 +98,9 @@ typedef struct {
 typedef struct pa_op pa_op;
 
 typedef struct {
-    int32_t p, q1d, ops, nelem, ndof, ness, ncomp, variant, elems_per_block;
+    int32_t p, q1d, ops, nelem, ndof, ness, ncomp, variant;
+    int32_t elems_per_block;   /* elements per element group of the selected variant's kernel */
+    int32_t threads_per_block; /* its workgroup size */
     int64_t qdata_bytes; /* bytes of stored quadrature-point data D */
     int64_t map_bytes;   /* bytes of the DOF map G */
 } pa_info_t;
@@ -162,6 +164,16 @@ int pa_get_ess(pa_op *op, int32_t *host_out);
 
 /* Select the apply kernel (PA_VARIANT_*).  Takes effect for later calls. */
 int pa_set_variant(pa_op *op, int variant);
+
+/* Limit every apply launch on this handle to at most max_workgroups workgroups (0, the
+   default, restores the persistent grid: the number of workgroups the device keeps
+   resident, or fewer when the mesh has fewer element groups).  The apply kernels are
+   persistent: each workgroup walks a strided list of element groups and prefetches the
+   DOF map, x and D of its next group while it contracts the current one.  Large meshes
+   always take that path; a cap lets a small mesh take it too (several groups per
+   workgroup), which is what tests of that path use.  Results do not depend on the cap
+   beyond the order of the atomic additions.  Takes effect for later calls. */
+int pa_set_grid_cap(pa_op *op, int max_workgroups);
 
 int pa_info(const pa_op *op, pa_info_t *info);
 void pa_destroy(pa_op *op);

@@ -67,6 +67,32 @@ hipError_t launch_apply_lp(const pa_op *op, int fmt, const float *x, float *y, h
     return hipSuccess;
 }
 
+bool apply_group_shape_p1(int, int, int, int *, int *);
+bool apply_group_shape_p2(int, int, int, int *, int *);
+bool apply_group_shape_p3(int, int, int, int *, int *);
+bool apply_group_shape_p4(int, int, int, int *, int *);
+bool apply_group_shape_p5(int, int, int, int *, int *);
+bool apply_group_shape_p6(int, int, int, int *, int *);
+bool apply_group_shape_p7(int, int, int, int *, int *);
+bool apply_group_shape_p8(int, int, int, int *, int *);
+
+// elements per element group and workgroup size of the kernel that a launch of `variant`
+// runs (variant -1: the 16-bit apply), as that kernel's template computes them
+static bool apply_group_shape(const pa_op *op, int variant, int *elems, int *threads)
+{
+    switch (op->p) {
+    case 1: return apply_group_shape_p1(op->q, op->ops, variant, elems, threads);
+    case 2: return apply_group_shape_p2(op->q, op->ops, variant, elems, threads);
+    case 3: return apply_group_shape_p3(op->q, op->ops, variant, elems, threads);
+    case 4: return apply_group_shape_p4(op->q, op->ops, variant, elems, threads);
+    case 5: return apply_group_shape_p5(op->q, op->ops, variant, elems, threads);
+    case 6: return apply_group_shape_p6(op->q, op->ops, variant, elems, threads);
+    case 7: return apply_group_shape_p7(op->q, op->ops, variant, elems, threads);
+    case 8: return apply_group_shape_p8(op->q, op->ops, variant, elems, threads);
+    }
+    return false;
+}
+
 }  // namespace hexpa
 
 using namespace hexpa;
@@ -383,6 +409,14 @@ extern "C" int pa_set_variant(pa_op *op, int variant)
     return PA_OK;
 }
 
+extern "C" int pa_set_grid_cap(pa_op *op, int max_workgroups)
+{
+    if (!op) return arg_error("pa_set_grid_cap: NULL op");
+    if (max_workgroups < 0) return arg_error("pa_set_grid_cap: max_workgroups must be >= 0");
+    op->grid_cap = max_workgroups;
+    return PA_OK;
+}
+
 extern "C" int pa_info(const pa_op *op, pa_info_t *info)
 {
     if (!op || !info) return arg_error("pa_info: NULL argument");
@@ -390,17 +424,10 @@ extern "C" int pa_info(const pa_op *op, pa_info_t *info)
     info->ness = op->ness; info->ncomp = op->ncomp; info->variant = op->variant;
     const int d = op->d, q = op->q;
     const int ncomp = op->ncomp;
-    // elements per workgroup of the register-staged fused kernel (mirrors Shape<>::E with
-    // the padded LDS tensors and the LDS budget of ApplyCfg)
-    const bool diff = op->ops & PA_DIFFUSION, mass = op->ops & PA_MASS;
-    const int ng = diff ? (mass ? 4 : 3) : 1;
-    const int dp = d % 4 ? d : d + 1, qp = q % 4 ? q : q + 1;  // pad_stride
-    auto mx = [](int a, int b) { return a > b ? a : b; };
-    const int sa = mx(d * d * dp, mx((diff ? 3 * q * q : q * q) * dp, ng * q * qp * d)) | 1;
-    const int sb = mx((diff ? 2 * q : q) * d * dp, mx(ng * q * q * qp, (diff ? 2 : 1) * d * d * qp)) | 1;
-    const int budget = (diff && d <= 5) ? 24 * 1024 : 48 * 1024;
-    int e = budget / (8 * (sa + sb) + 4 * d * d * d);
-    info->elems_per_block = e < 1 ? 1 : (e > 32 ? 32 : e);
+    int elems = 1, threads = 256;
+    if (!apply_group_shape(op, op->variant, &elems, &threads)) return arg_error("pa_info: no kernel for this operator");
+    info->elems_per_block = elems;
+    info->threads_per_block = threads;
     info->qdata_bytes = (int64_t)op->nelem * ncomp * q * q * q * 8;
     info->map_bytes = (int64_t)op->nelem * d * d * d * 4;
     return PA_OK;

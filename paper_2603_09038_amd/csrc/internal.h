@@ -48,6 +48,7 @@ struct pa_op {
     int nelem = 0, ndof = 0, ness = 0;
     int nx = 0, ny = 0, nz = 0;
     int variant = PA_VARIANT_MFMA;
+    int grid_cap = 0;                // > 0: at most this many workgroups per apply launch (pa_set_grid_cap)
     int device = 0;
     int32_t *d_elem_dofs = nullptr;  // [nelem][d^3]
     double *d_qdata = nullptr;       // [nelem][ncomp][q^3]

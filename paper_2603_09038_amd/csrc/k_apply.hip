@@ -737,6 +737,12 @@ static int persistent_blocks(int nt, int ngroups)
     return ngroups < cap ? ngroups : cap;
 }
 
+// grid of an apply launch: the persistent grid, capped by pa_set_grid_cap
+static int capped(const pa_op *op, int nblocks)
+{
+    return (op->grid_cap > 0 && op->grid_cap < nblocks) ? op->grid_cap : nblocks;
+}
+
 // The unfused apply: forward stage, D-step, transposed stage (y must hold zeros).
 template <int D, int Q, int OPS, int EX>
 static hipError_t launch_unfused(const pa_op *op, const double *x, double *y, double *qbuf, hipStream_t s)
@@ -748,14 +754,14 @@ static hipError_t launch_unfused(const pa_op *op, const double *x, double *y, do
     if (ngroups == 0) return hipSuccess;
     constexpr auto k1 = k_apply<D, Q, OPS, EX, true, 1>;
     constexpr auto k3 = k_apply<D, Q, OPS, EX, true, 2>;
-    hipLaunchKernelGGL(k1, dim3(persistent_blocks<k1>(CFG::NT, ngroups)), dim3(CFG::NT), 0, s, n, ngroups,
+    hipLaunchKernelGGL(k1, dim3(capped(op, persistent_blocks<k1>(CFG::NT, ngroups))), dim3(CFG::NT), 0, s, n, ngroups,
                        (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf, op->d_vert,
                        op->d_hex, op->coeff);
     const int64_t npts = (int64_t)n * S::Q3;
     auto k2 = k_dstep<Q, OPS, double>;
     hipLaunchKernelGGL(k2, dim3((unsigned)std::min<int64_t>((npts + 255) / 256, 65536)), dim3(256), 0, s, npts,
                        (const double *)op->d_qdata, qbuf);
-    hipLaunchKernelGGL(k3, dim3(persistent_blocks<k3>(CFG::NT, ngroups)), dim3(CFG::NT), 0, s, n, ngroups,
+    hipLaunchKernelGGL(k3, dim3(capped(op, persistent_blocks<k3>(CFG::NT, ngroups))), dim3(CFG::NT), 0, s, n, ngroups,
                        (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf, op->d_vert,
                        op->d_hex, op->coeff);
     return hipGetLastError();
@@ -771,7 +777,7 @@ static hipError_t launch_mf(const pa_op *op, const double *x, double *y, hipStre
     const int ngroups = (n + S::E - 1) / S::E;
     if (ngroups == 0) return hipSuccess;
     constexpr auto k = k_apply<D, Q, OPS, EX, true, 3>;
-    hipLaunchKernelGGL(k, dim3(persistent_blocks<k>(CFG::NT, ngroups)), dim3(CFG::NT), 0, s, n, ngroups,
+    hipLaunchKernelGGL(k, dim3(capped(op, persistent_blocks<k>(CFG::NT, ngroups))), dim3(CFG::NT), 0, s, n, ngroups,
                        (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, (double *)nullptr,
                        op->d_vert, op->d_hex, op->coeff);
     return hipGetLastError();
@@ -791,12 +797,12 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
     if (ngroups == 0) return hipSuccess;
     if constexpr (!DMA) {
         constexpr auto kern = k_apply<D, Q, OPS, EX, ATOMIC, 0>;
-        const int nblocks = persistent_blocks<kern>(NT, ngroups);
+        const int nblocks = capped(op, persistent_blocks<kern>(NT, ngroups));
         hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab, x,
                            y, (T *)nullptr, (const double *)nullptr, (const int32_t *)nullptr, CoeffDev{});
     } else {
         constexpr auto kern = k_apply_dma<D, Q, OPS, EX, ATOMIC>;
-        const int nblocks = persistent_blocks<kern>(NT, ngroups);
+        const int nblocks = capped(op, persistent_blocks<kern>(NT, ngroups));
         hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab, x,
                            y);
     }
@@ -870,6 +876,49 @@ static hipError_t launch_p_lp(const pa_op *op, int fmt, const float *x, float *y
     return hipSuccess;
 }
 
+// elements per group and workgroup size of the kernel a launch of this variant runs
+template <int D, int Q, int OPS, int EX, bool FUSED_STORED>
+static void group_shape(int *elems, int *threads)
+{
+    using T = typename ExT<EX>::T;
+    using CFG = ApplyCfg<D, OPS, EX>;
+    constexpr bool DMA = FUSED_STORED && DmaShape<D, Q, OPS, T>::ok;
+    *elems = DMA ? DmaShape<D, Q, OPS, T>::E : Shape<D, Q, OPS, (int)sizeof(T), CFG::NT, CFG::BUDGET>::E;
+    *threads = DMA ? kThreads : CFG::NT;
+}
+
+template <int D, int Q, int OPS>
+static void group_shape_t(int variant, int *elems, int *threads)
+{
+    switch (variant) {
+    case PA_VARIANT_MFMA_UNFUSED:
+    case PA_VARIANT_MFMA_MF: return group_shape<D, Q, OPS, EX_MFMA64, false>(elems, threads);
+    case PA_VARIANT_VALU_UNFUSED:
+    case PA_VARIANT_VALU_MF: return group_shape<D, Q, OPS, EX_VALU64, false>(elems, threads);
+    case PA_VARIANT_VALU: return group_shape<D, Q, OPS, EX_VALU64, true>(elems, threads);
+    case -1: return group_shape<D, Q, OPS, EX_MFMA16F, true>(elems, threads);  // the 16-bit apply
+    default: return group_shape<D, Q, OPS, EX_MFMA64, true>(elems, threads);
+    }
+}
+
+template <int P>
+static bool group_shape_p(int q, int ops, int variant, int *elems, int *threads)
+{
+    constexpr int D = P + 1;
+    if (q != P + 1 && q != P + 2) return false;
+    if (ops < 1 || ops > 3) return false;
+    if (q == P + 1) {
+        if (ops == 1) group_shape_t<D, P + 1, 1>(variant, elems, threads);
+        if (ops == 2) group_shape_t<D, P + 1, 2>(variant, elems, threads);
+        if (ops == 3) group_shape_t<D, P + 1, 3>(variant, elems, threads);
+    } else {
+        if (ops == 1) group_shape_t<D, P + 2, 1>(variant, elems, threads);
+        if (ops == 2) group_shape_t<D, P + 2, 2>(variant, elems, threads);
+        if (ops == 3) group_shape_t<D, P + 2, 3>(variant, elems, threads);
+    }
+    return true;
+}
+
 #ifndef HEXPA_APPLY_P
 #error "compile k_apply.hip once per order with -DHEXPA_APPLY_P=<p>"
 #endif
@@ -885,6 +934,10 @@ hipError_t HEXPA_CAT(launch_apply_lp_p, HEXPA_APPLY_P)(const pa_op *op, int fmt,
                                                       hipStream_t s, bool *ok)
 {
     return launch_p_lp<HEXPA_APPLY_P>(op, fmt, x, y, s, ok);
+}
+bool HEXPA_CAT(apply_group_shape_p, HEXPA_APPLY_P)(int q, int ops, int variant, int *elems, int *threads)
+{
+    return group_shape_p<HEXPA_APPLY_P>(q, ops, variant, elems, threads);
 }
 
 }  // namespace hexpa

@@ -148,6 +148,10 @@ __global__ void k_cg_update1(T *__restrict__ x, T *__restrict__ r, const T *__re
     const double pAp = a[0], rz = s->rz;
     const bool bad = !(pAp > 0.0) || !isfinite(pAp) || !isfinite(rz);
     const double alpha = bad ? 0.0 : rz / pAp;
+    // After a breakdown (this step's, seen identically by every block, or an earlier one:
+    // the flag is sticky) x and r keep their last values, so the caller gets the last
+    // finite iterate even when p or Ap hold non-finite entries (0 * NaN is NaN).
+    const bool frozen = bad || s->breakdown != 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s->pAp = pAp;
         s->alpha = alpha;
@@ -157,9 +161,12 @@ __global__ void k_cg_update1(T *__restrict__ x, T *__restrict__ r, const T *__re
     __syncthreads();  // sh is reused below
     double v[2] = {0.0, 0.0};
     auto one = [&](int64_t i, T pi, T xi, T ai, T r0, T di) {
-        x[i] = (T)fma(alpha, (double)pi, (double)xi);
-        const T ri = (T)fma(-alpha, (double)ai, (double)r0);
-        r[i] = ri;
+        T ri = r0;
+        if (!frozen) {
+            x[i] = (T)fma(alpha, (double)pi, (double)xi);
+            ri = (T)fma(-alpha, (double)ai, (double)r0);
+            r[i] = ri;
+        }
         const double zi = dinv ? (double)(di * ri) : (double)ri;
         v[0] = fma((double)ri, zi, v[0]);
         v[1] = fma((double)ri, (double)ri, v[1]);
@@ -300,20 +307,27 @@ __global__ void k_axpy_f32(double *x, double a, const float *d, int64_t n)
 }
 
 // ---- flexible CG (FCG(1)) pieces
-// x += alpha p; rold = r; r -= alpha Ap; partial sums of r.r
+// x += alpha p; rold = r; r -= alpha Ap; partial sums of r.r.  Once a breakdown has been
+// flagged (sticky; no block of this kernel writes the flag) x, r and rold are left as they
+// are: a non-finite preconditioner output reaches p before the host sees the flag, and
+// alpha = 0 would still turn x into 0 * NaN.  The fallback restarts from that x.
 __global__ void k_fcg_update(double *__restrict__ x, double *__restrict__ r, double *__restrict__ rold,
                              const double *__restrict__ p, const double *__restrict__ Ap, int64_t n,
                              const CgScalars *__restrict__ s, double *partial)
 {
     __shared__ double sh[256];
     const double alpha = s->alpha;
+    const bool frozen = s->breakdown != 0;
     double v[1] = {0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        x[i] = fma(alpha, p[i], x[i]);
         const double ri = r[i];
-        rold[i] = ri;
-        const double rn = fma(-alpha, Ap[i], ri);
-        r[i] = rn;
+        double rn = ri;
+        if (!frozen) {
+            x[i] = fma(alpha, p[i], x[i]);
+            rold[i] = ri;
+            rn = fma(-alpha, Ap[i], ri);
+            r[i] = rn;
+        }
         v[0] = fma(rn, rn, v[0]);
     }
     block_sum<1>(v, sh);

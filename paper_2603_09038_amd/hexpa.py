@@ -27,7 +27,7 @@ PA_LP_FP16, PA_LP_BF16 = 0, 1
 
 # every symbol include/hexpa.h declares
 EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_lp", "pa_apply_constrained", "pa_diag", "pa_load", "pa_qpoints", "pa_nodes",
-           "pa_get_elem_dofs", "pa_get_ess", "pa_set_variant", "pa_info", "pa_destroy", "pa_last_error",
+           "pa_get_elem_dofs", "pa_get_ess", "pa_set_variant", "pa_set_grid_cap", "pa_info", "pa_destroy", "pa_last_error",
            "cg_solve", "pa_debug_mfma_f64", "pa_debug_mfma16",
            "pa_lp_create", "pa_lp_bind", "pa_lp_configure", "pa_lp_num_params", "pa_lp_get_params",
            "pa_lp_set_params", "pa_lp_logk", "pa_lp_apply", "pa_lp_coarse", "pa_lp_net", "pa_lp_loss_grad",
@@ -55,7 +55,7 @@ class CoeffDesc(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("p", "q1d", "ops", "nelem", "ndof", "ness", "ncomp", "variant",
-                                              "elems_per_block")] + \
+                                              "elems_per_block", "threads_per_block")] + \
                [("qdata_bytes", ctypes.c_int64), ("map_bytes", ctypes.c_int64)]
 
 
@@ -99,6 +99,7 @@ def _load():
         "pa_get_elem_dofs": [vp, vp],
         "pa_get_ess": [vp, vp],
         "pa_set_variant": [vp, i32],
+        "pa_set_grid_cap": [vp, i32],
         "pa_info": [vp, ctypes.POINTER(Info)],
         "cg_solve": [vp, vp, vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgResult), vp],
         "pa_debug_mfma_f64": [i32, vp, vp, vp, vp],
@@ -260,6 +261,10 @@ def pa_get_ess(h):
 
 def pa_set_variant(h, variant):
     _check(_lib.pa_set_variant(h, int(variant)))
+
+
+def pa_set_grid_cap(h, max_workgroups):
+    _check(_lib.pa_set_grid_cap(h, int(max_workgroups)))
 
 
 def pa_destroy(h):
@@ -430,6 +435,9 @@ class PAOperator:
     def set_variant(self, v):
         pa_set_variant(self.h, v)
         self.info = pa_info(self.h)
+
+    def set_grid_cap(self, n):
+        pa_set_grid_cap(self.h, n)
 
     def cg(self, b, x=None, **kw):
         import torch
