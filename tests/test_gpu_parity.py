@@ -204,6 +204,25 @@ def test_persistent_multigroup_lp_apply(hx, p):
     op.close()
 
 
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_diag_parity_orders(hx, p):
+    """The sum-factorised diagonal against the oracle's diagonal of the dense element
+    matrices, every operator combination, both quadrature sizes, plain and constrained."""
+    from oracle import solvers
+    n = {1: 5, 2: 4, 3: 3, 4: 3, 5: 2, 6: 2, 7: 2, 8: 2}[p]
+    mesh = synth.box_mesh(n, perturb=0.1, seed=30 + p)
+    coeff = {"kind": hx.PA_COEFF_SINE, "value": 1.0, "amp": 0.5, "freq": 2.0}
+    ess = oracle.box_boundary(n, p).astype(bool)
+    for q in (p + 1, p + 2):
+        for ops in (1, 2, 3):
+            op = hx.PAOperator(mesh, p, q, coeff=coeff, ops=ops, ess_mode=1)
+            ref = oracle.Problem(mesh, p, q, coeff=oracle.Coeff.sine(), ops=_ops_o(ops)).diag()
+            assert _rel(op.diag().cpu().numpy(), ref) <= TOL, (p, q, ops)
+            dc = op.diag(constrained=True).cpu().numpy()
+            assert _rel(dc, solvers.constrained_diag(ref, ess)) <= TOL, (p, q, ops)
+            op.close()
+
+
 def test_grid_coefficient_and_diag_load_points(hx):
     p, q, n = 3, 5, 3
     mesh = synth.box_mesh(n, perturb=0.1, seed=9)
