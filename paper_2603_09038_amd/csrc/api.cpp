@@ -16,27 +16,36 @@ namespace hexpa {
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
-hipError_t launch_apply_p1(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
-hipError_t launch_apply_p2(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
-hipError_t launch_apply_p3(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
-hipError_t launch_apply_p4(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
-hipError_t launch_apply_p5(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
-hipError_t launch_apply_p6(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
-hipError_t launch_apply_p7(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
-hipError_t launch_apply_p8(const pa_op *, int, const double *, double *, const int32_t *, int, hipStream_t, bool *);
+hipError_t launch_apply_p1(const pa_op *, int, const double *, double *, const int32_t *, int, double *, hipStream_t,
+                           bool *);
+hipError_t launch_apply_p2(const pa_op *, int, const double *, double *, const int32_t *, int, double *, hipStream_t,
+                           bool *);
+hipError_t launch_apply_p3(const pa_op *, int, const double *, double *, const int32_t *, int, double *, hipStream_t,
+                           bool *);
+hipError_t launch_apply_p4(const pa_op *, int, const double *, double *, const int32_t *, int, double *, hipStream_t,
+                           bool *);
+hipError_t launch_apply_p5(const pa_op *, int, const double *, double *, const int32_t *, int, double *, hipStream_t,
+                           bool *);
+hipError_t launch_apply_p6(const pa_op *, int, const double *, double *, const int32_t *, int, double *, hipStream_t,
+                           bool *);
+hipError_t launch_apply_p7(const pa_op *, int, const double *, double *, const int32_t *, int, double *, hipStream_t,
+                           bool *);
+hipError_t launch_apply_p8(const pa_op *, int, const double *, double *, const int32_t *, int, double *, hipStream_t,
+                           bool *);
 
 hipError_t launch_apply(const pa_op *op, int variant, const double *x, double *y, const int32_t *elist, int n,
-                        hipStream_t s, bool *ok)
+                        hipStream_t s, bool *ok, double *qbuf)
 {
+    if (!qbuf) qbuf = op->d_qbuf;
     switch (op->p) {
-    case 1: return launch_apply_p1(op, variant, x, y, elist, n, s, ok);
-    case 2: return launch_apply_p2(op, variant, x, y, elist, n, s, ok);
-    case 3: return launch_apply_p3(op, variant, x, y, elist, n, s, ok);
-    case 4: return launch_apply_p4(op, variant, x, y, elist, n, s, ok);
-    case 5: return launch_apply_p5(op, variant, x, y, elist, n, s, ok);
-    case 6: return launch_apply_p6(op, variant, x, y, elist, n, s, ok);
-    case 7: return launch_apply_p7(op, variant, x, y, elist, n, s, ok);
-    case 8: return launch_apply_p8(op, variant, x, y, elist, n, s, ok);
+    case 1: return launch_apply_p1(op, variant, x, y, elist, n, qbuf, s, ok);
+    case 2: return launch_apply_p2(op, variant, x, y, elist, n, qbuf, s, ok);
+    case 3: return launch_apply_p3(op, variant, x, y, elist, n, qbuf, s, ok);
+    case 4: return launch_apply_p4(op, variant, x, y, elist, n, qbuf, s, ok);
+    case 5: return launch_apply_p5(op, variant, x, y, elist, n, qbuf, s, ok);
+    case 6: return launch_apply_p6(op, variant, x, y, elist, n, qbuf, s, ok);
+    case 7: return launch_apply_p7(op, variant, x, y, elist, n, qbuf, s, ok);
+    case 8: return launch_apply_p8(op, variant, x, y, elist, n, qbuf, s, ok);
     }
     *ok = false;
     return hipSuccess;

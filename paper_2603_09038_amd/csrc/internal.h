@@ -78,9 +78,11 @@ hipError_t launch_nodes(const pa_op *op, double *xyz, hipStream_t s);
 // log kappa at every (element, local node) as FP32 [nelem][d^3]
 hipError_t logk_tiles(const pa_op *op, float *out, hipStream_t s);
 hipError_t launch_load(const pa_op *op, const double *fq, double *b, hipStream_t s);
-// apply: y += A x over the listed elements (elem_list == nullptr: all)
+// apply: y += A x over the listed elements (elem_list == nullptr: all); the unfused
+// variants stage the quadrature-point tensor in qbuf (nullptr: the handle's d_qbuf)
 hipError_t launch_apply(const pa_op *op, int variant, const double *x, double *y,
-                        const int32_t *elem_list, int nlist, hipStream_t s, bool *supported);
+                        const int32_t *elem_list, int nlist, hipStream_t s, bool *supported,
+                        double *qbuf = nullptr);
 hipError_t launch_apply_lp(const pa_op *op, int fmt, const float *x, float *y, hipStream_t s, bool *supported);
 hipError_t launch_diag(const pa_op *op, double *diag, hipStream_t s);
 hipError_t launch_debug_mfma16(int bf, const float *A, const float *B, float *D, hipStream_t s);

@@ -811,11 +811,11 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
 
 template <int D, int Q, int OPS>
 static hipError_t launch_t(const pa_op *op, int variant, const double *x, double *y, const int32_t *elist, int n,
-                           hipStream_t s)
+                           double *qbuf, hipStream_t s)
 {
     switch (variant) {
-    case PA_VARIANT_MFMA_UNFUSED: return launch_unfused<D, Q, OPS, EX_MFMA64>(op, x, y, op->d_qbuf, s);
-    case PA_VARIANT_VALU_UNFUSED: return launch_unfused<D, Q, OPS, EX_VALU64>(op, x, y, op->d_qbuf, s);
+    case PA_VARIANT_MFMA_UNFUSED: return launch_unfused<D, Q, OPS, EX_MFMA64>(op, x, y, qbuf, s);
+    case PA_VARIANT_VALU_UNFUSED: return launch_unfused<D, Q, OPS, EX_VALU64>(op, x, y, qbuf, s);
     case PA_VARIANT_MFMA_MF: return launch_mf<D, Q, OPS, EX_MFMA64>(op, x, y, s);
     case PA_VARIANT_VALU_MF: return launch_mf<D, Q, OPS, EX_VALU64>(op, x, y, s);
     case PA_VARIANT_VALU: return launch_k<D, Q, OPS, EX_VALU64, true>(op, op->d_qdata, x, y, elist, n, s);
@@ -833,21 +833,21 @@ static hipError_t launch_t_lp(const pa_op *op, int fmt, const float *x, float *y
 
 template <int P>
 static hipError_t launch_p(const pa_op *op, int variant, const double *x, double *y, const int32_t *elist, int n,
-                           hipStream_t s, bool *ok)
+                           double *qbuf, hipStream_t s, bool *ok)
 {
     constexpr int D = P + 1;
     *ok = true;
     if (op->q == P + 1) {
         switch (op->ops) {
-        case 1: return launch_t<D, P + 1, 1>(op, variant, x, y, elist, n, s);
-        case 2: return launch_t<D, P + 1, 2>(op, variant, x, y, elist, n, s);
-        case 3: return launch_t<D, P + 1, 3>(op, variant, x, y, elist, n, s);
+        case 1: return launch_t<D, P + 1, 1>(op, variant, x, y, elist, n, qbuf, s);
+        case 2: return launch_t<D, P + 1, 2>(op, variant, x, y, elist, n, qbuf, s);
+        case 3: return launch_t<D, P + 1, 3>(op, variant, x, y, elist, n, qbuf, s);
         }
     } else if (op->q == P + 2) {
         switch (op->ops) {
-        case 1: return launch_t<D, P + 2, 1>(op, variant, x, y, elist, n, s);
-        case 2: return launch_t<D, P + 2, 2>(op, variant, x, y, elist, n, s);
-        case 3: return launch_t<D, P + 2, 3>(op, variant, x, y, elist, n, s);
+        case 1: return launch_t<D, P + 2, 1>(op, variant, x, y, elist, n, qbuf, s);
+        case 2: return launch_t<D, P + 2, 2>(op, variant, x, y, elist, n, qbuf, s);
+        case 3: return launch_t<D, P + 2, 3>(op, variant, x, y, elist, n, qbuf, s);
         }
     }
     *ok = false;
@@ -926,9 +926,9 @@ static bool group_shape_p(int q, int ops, int variant, int *elems, int *threads)
 #define HEXPA_CAT2(a, b) a##b
 #define HEXPA_CAT(a, b) HEXPA_CAT2(a, b)
 hipError_t HEXPA_CAT(launch_apply_p, HEXPA_APPLY_P)(const pa_op *op, int variant, const double *x, double *y,
-                                                   const int32_t *elist, int n, hipStream_t s, bool *ok)
+                                                   const int32_t *elist, int n, double *qbuf, hipStream_t s, bool *ok)
 {
-    return launch_p<HEXPA_APPLY_P>(op, variant, x, y, elist, n, s, ok);
+    return launch_p<HEXPA_APPLY_P>(op, variant, x, y, elist, n, qbuf, s, ok);
 }
 hipError_t HEXPA_CAT(launch_apply_lp_p, HEXPA_APPLY_P)(const pa_op *op, int fmt, const float *x, float *y,
                                                       hipStream_t s, bool *ok)
