@@ -138,6 +138,21 @@ int pa_apply_add(pa_op *op, const double *x, double *y, void *stream);
 #define PA_LP_BF16 1
 int pa_apply_lp(pa_op *op, const float *x, float *y, int fmt, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+   loops, harnesses that forbid hipMalloc): y = A x with the unfused apply (variant
+   PA_VARIANT_MFMA_UNFUSED or PA_VARIANT_VALU_UNFUSED; forward contractions, D-step and
+   transposed contractions as three kernels), whose quadrature-point tensor is staged in
+   a fixed 128 MiB device array of the library (one per GPU, held until the process ends)
+   instead of handle memory that pa_apply allocates on first use.  Allocates nothing.
+   The tensor needs nelem x (1 | 3 | 4 for mass | diffusion | both) x q1d^3 doubles; a
+   larger operator gets PA_ERR_ARG before any launch (at most 16 Mi doubles, e.g. 25,890
+   elements of p = 4 diffusion with q1d = 6).  The operator's device must be current.
+   Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other
+   streams or threads, any operator) race and must be serialised by the caller.  Each
+   call writes every entry it reads before reading it, so nothing needs clearing
+   between calls.  y is overwritten; x and y must not alias.  Asynchronous. */
+int pa_apply_unfused_noalloc(pa_op *op, int variant, const double *x, double *y, void *stream);
+
 /* y = A_c x with A_c = (I - E) A (I - E) + E, E = indicator of the essential DOFs.
    Uses handle-owned scratch; calls on one handle must not overlap.  Asynchronous. */
 int pa_apply_constrained(pa_op *op, const double *x, double *y, void *stream);

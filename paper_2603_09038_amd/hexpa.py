@@ -26,7 +26,7 @@ PA_LP_LOSS_ENERGY, PA_LP_LOSS_L2 = 0, 1
 PA_LP_FP16, PA_LP_BF16 = 0, 1
 
 # every symbol include/hexpa.h declares
-EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_lp", "pa_apply_constrained", "pa_diag", "pa_load", "pa_qpoints", "pa_nodes",
+EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_lp", "pa_apply_unfused_noalloc", "pa_apply_constrained", "pa_diag", "pa_load", "pa_qpoints", "pa_nodes",
            "pa_get_elem_dofs", "pa_get_ess", "pa_set_variant", "pa_set_grid_cap", "pa_info", "pa_destroy", "pa_last_error",
            "cg_solve", "pa_debug_mfma_f64", "pa_debug_mfma16",
            "pa_lp_create", "pa_lp_bind", "pa_lp_configure", "pa_lp_num_params", "pa_lp_get_params",
@@ -91,6 +91,7 @@ def _load():
         "pa_apply": [vp, vp, vp, vp],
         "pa_apply_add": [vp, vp, vp, vp],
         "pa_apply_lp": [vp, vp, vp, i32, vp],
+        "pa_apply_unfused_noalloc": [vp, i32, vp, vp, vp],
         "pa_apply_constrained": [vp, vp, vp, vp],
         "pa_diag": [vp, vp, i32, vp],
         "pa_load": [vp, vp, vp, vp],
@@ -222,6 +223,10 @@ def pa_apply_add(h, x, y, stream=None):
 def pa_apply_lp(h, x, y, fmt=PA_LP_FP16, stream=None):
     import torch
     _check(_lib.pa_apply_lp(h, _dptr(x, torch.float32), _dptr(y, torch.float32), int(fmt), _stream(stream)))
+
+
+def pa_apply_unfused_noalloc(h, variant, x, y, stream=None):
+    _check(_lib.pa_apply_unfused_noalloc(h, int(variant), _dptr(x), _dptr(y), _stream(stream)))
 
 
 def pa_apply_constrained(h, x, y, stream=None):
