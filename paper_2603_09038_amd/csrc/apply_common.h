@@ -32,29 +32,11 @@
 
 namespace hexpa {
 
-#ifndef HEXPA_THREADS
-#define HEXPA_THREADS 256
-#endif
-constexpr int kThreads = HEXPA_THREADS;  // threads per workgroup of the fused apply
+constexpr int kThreads = 256;  // threads per workgroup of the fused apply (four-wave instances)
 constexpr int kWaves = kThreads / 64;
-
-// Tuning constants (overridable at compile time for sweeps).
-#ifndef HEXPA_LDS_BUDGET
-#define HEXPA_LDS_BUDGET (48 * 1024)
-#endif
-#ifndef HEXPA_MFMA_BATCH
-#define HEXPA_MFMA_BATCH 2
-#endif
-#ifndef HEXPA_VALU_BATCH
-#define HEXPA_VALU_BATCH 2
-#endif
-constexpr int kLdsBudget = HEXPA_LDS_BUDGET;  // bytes of LDS per workgroup
-constexpr int kMfmaBatch = HEXPA_MFMA_BATCH;  // MFMA tiles in flight per wave
-constexpr int kValuBatch = HEXPA_VALU_BATCH;  // GEMM columns in flight per thread
-#ifndef HEXPA_VALU_SPLIT
-#define HEXPA_VALU_SPLIT 0
-#endif
-constexpr int kValuSplit = HEXPA_VALU_SPLIT;  // max threads sharing one column's outputs (0/1: none)
+constexpr int kLdsBudget = 48 * 1024;  // bytes of LDS per workgroup for the element tensors
+constexpr int kMfmaBatch = 2;          // MFMA tiles in flight per wave
+constexpr int kValuBatch = 2;          // GEMM columns in flight per thread
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -250,46 +232,25 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
 }
 
 // ------------------------------------------------------------------ VALU executor
-// Thread per GEMM column and output part: when a pass has fewer columns than threads, the
-// O outputs of a column may be split over up to kValuSplit threads (the part is uniform
-// over a wave; consecutive threads take consecutive columns, so LDS reads stay
-// conflict-free); each thread keeps its outputs in registers.  BATCH work items per
-// thread are loaded before any FMA so the LDS latency of one hides behind another.
-template <class P, int E, int NT>
-struct ValuShape {
-    static constexpr int NCOLS = E * P::NCOL;
-    static constexpr int NCOLP = ((NCOLS + 63) / 64) * 64;  // whole waves per output part
-    static constexpr int S = (kValuSplit >= 4 && 4 * NCOLP <= NT && P::O >= 8)   ? 4
-                             : (kValuSplit >= 2 && 2 * NCOLP <= NT && P::O >= 4) ? 2
-                                                                                        : 1;
-    static constexpr int OP = (P::O + S - 1) / S;  // outputs per thread
-    static constexpr int NTOT = S == 1 ? NCOLS : NCOLP * S;
-};
-
+// One thread per GEMM column, all O outputs in registers.  BATCH columns per thread are
+// loaded before any FMA so the LDS latency of one hides behind another.
 template <class P, int E, int NTH, class Out>
 __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevTables *tab, const Out &out, int tid)
 {
     constexpr int C = P::C, CS = P::CS, NT = P::NT, O = P::O, NCOLO = OutLayout<P>::NCOLO;
-    using V = ValuShape<P, E, NTH>;
-    constexpr int NTOT = V::NTOT, OP = V::OP;
-    constexpr int NR = (NTOT + NTH - 1) / NTH;
+    constexpr int NCOLS = E * P::NCOL;
+    constexpr int NR = (NCOLS + NTH - 1) / NTH;
     constexpr int BATCH = NR < kValuBatch ? NR : kValuBatch;
 #pragma unroll 1
     for (int r0 = 0; r0 < NR; r0 += BATCH) {
         double xin[BATCH][NT * C];
-        int eI[BATCH], nI[BATCH], o0[BATCH];
+        int eI[BATCH], nI[BATCH];
         bool cv[BATCH];
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
-            const int it = tid + NTH * (r0 + bi);
-            int col = it, part = 0;
-            if constexpr (V::S > 1) {
-                part = __builtin_amdgcn_readfirstlane(it / V::NCOLP);
-                col = it - part * V::NCOLP;
-            }
-            cv[bi] = (r0 + bi < NR) && it < NTOT && col < V::NCOLS;
+            int col = tid + NTH * (r0 + bi);
+            cv[bi] = (r0 + bi < NR) && col < NCOLS;
             if (!cv[bi]) col = 0;
-            o0[bi] = part * OP;
             eI[bi] = col / P::NCOL;
             nI[bi] = col - eI[bi] * P::NCOL;
             const double *base = in + eI[bi] * szin + nI[bi] * CS;
@@ -300,26 +261,17 @@ __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevT
         }
 #pragma unroll
         for (int bi = 0; bi < BATCH; ++bi) {
-            double acc[OP];
+            double acc[O];
 #pragma unroll
-            for (int o = 0; o < OP; ++o) acc[o] = 0.0;
-            if constexpr (V::S == 1) {
+            for (int o = 0; o < O; ++o) acc[o] = 0.0;
 #pragma unroll
-                for (int k = 0; k < NT * C; ++k)
+            for (int k = 0; k < NT * C; ++k)
 #pragma unroll
-                    for (int o = 0; o < OP; ++o) acc[o] = fma(P::A(tab, o, k), xin[bi][k], acc[o]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < NT * C; ++k)
-#pragma unroll
-                    for (int o = 0; o < OP; ++o)
-                        if (o0[bi] + o < O) acc[o] = fma(P::A(tab, o0[bi] + o, k), xin[bi][k], acc[o]);
-            }
+                for (int o = 0; o < O; ++o) acc[o] = fma(P::A(tab, o, k), xin[bi][k], acc[o]);
             if (cv[bi]) {
                 const int ob = P::OUT + OutLayout<P>::opos(nI[bi]);
 #pragma unroll
-                for (int o = 0; o < OP; ++o)
-                    if (o0[bi] + o < O) out.put(eI[bi], ob + NCOLO * (o0[bi] + o), acc[o]);
+                for (int o = 0; o < O; ++o) out.put(eI[bi], ob + NCOLO * o, acc[o]);
             }
         }
     }

@@ -13,26 +13,6 @@
 #include "apply_passes.h"
 #include "geometry.h"
 
-#ifndef HEXPA_PREFETCH_D
-#define HEXPA_PREFETCH_D 0
-#endif
-#ifndef HEXPA_OVERSUB
-#define HEXPA_OVERSUB 1
-#endif
-#ifndef HEXPA_LATE_D
-#define HEXPA_LATE_D 0
-#endif
-#ifndef HEXPA_MIN_BLOCKS
-#define HEXPA_MIN_BLOCKS 3
-#endif
-
-#ifndef HEXPA_LDS_BARRIER
-#define HEXPA_LDS_BARRIER 1
-#endif
-#ifndef HEXPA_LP_CENTRE
-#define HEXPA_LP_CENTRE 1
-#endif
-
 namespace hexpa {
 
 // Workgroup barrier for LDS traffic only.  __syncthreads() also orders global memory at
@@ -40,19 +20,9 @@ namespace hexpa {
 // prefetched map/x load and every scatter atomic in flight would be waited for.  The
 // waves of a workgroup exchange data only through LDS, so waiting for LDS (lgkmcnt) is
 // enough; loads whose registers are used later are still waited for by the compiler.
-__device__ __forceinline__ void lds_barrier()
-{
-#if HEXPA_LDS_BARRIER
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-#else
-    __syncthreads();
-#endif
-}
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-constexpr bool kPrefetchD = HEXPA_PREFETCH_D != 0;  // double-buffer D in registers across groups
-constexpr bool kLateD = HEXPA_LATE_D != 0;          // load D at the D-step (no prefetch)
-constexpr int kOversub = HEXPA_OVERSUB;             // resident-workgroup multiples in the grid (0: one group each)
-constexpr int kMinWavesPerEU = HEXPA_MIN_BLOCKS;    // register budget: waves resident per SIMD
+constexpr int kMinWavesPerEU = 3;  // register budget: waves resident per SIMD
 
 // Contraction executors.
 enum : int { EX_MFMA64 = 0, EX_VALU64 = 1, EX_MFMA16F = 2, EX_MFMA16B = 3 };
@@ -111,12 +81,9 @@ __device__ __forceinline__ int qtpos(int r)
 // two-wave workgroups with a 24 KB element budget (two elements at p = 4; fewer waves wait
 // at each barrier, more workgroups per CU); everything else four waves and a 48 KB budget
 // (measured per order).
-#ifndef HEXPA_SMALL_WG_MAX_D
-#define HEXPA_SMALL_WG_MAX_D 5
-#endif
 template <int D, int OPS, int EX>
 struct ApplyCfg {
-    static constexpr bool SMALL = (OPS & 2) != 0 && D <= HEXPA_SMALL_WG_MAX_D && (EX == 0 || EX == 1);
+    static constexpr bool SMALL = (OPS & 2) != 0 && D <= 5 && (EX == 0 || EX == 1);
     static constexpr int NT = SMALL ? 128 : kThreads;
     static constexpr int BUDGET = SMALL ? 24 * 1024 : kLdsBudget;
 };
@@ -212,15 +179,12 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
     // two-wave workgroups: the independent y-direction passes (forward: on B x and on G x;
     // transposed: the two paths) each get a wave of their own instead of sharing wave 0
-#ifndef HEXPA_PASS_PAIRS
-#define HEXPA_PASS_PAIRS 1
-#endif
-    constexpr bool PAIRS = HEXPA_PASS_PAIRS && NT == 128 && S::kDiff;
+    constexpr bool PAIRS = NT == 128 && S::kDiff;
     __shared__ T bufA[E * S::SZ_A + S::SLACK];
     __shared__ T bufB[E * S::SZ_B + S::SLACK];
     __shared__ int32_t lmap[E * D3];
     __shared__ DevTables stab;  // 1-D tables in LDS: MFMA A-operands are re-read per pass
-    constexpr bool CENTRE = HEXPA_LP_CENTRE && EX == EX_MFMA16B && OPS == 2;
+    constexpr bool CENTRE = EX == EX_MFMA16B && OPS == 2;
     __shared__ T emean[CENTRE ? E : 1];
 
     const int tid = threadIdx.x;
@@ -256,7 +220,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     T xcur[NM];
     {
         const int e0 = g * E, nv = min(E, nelem - e0);
-        if constexpr (LOADD && !kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
+        if constexpr (LOADD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
         load_map<S, EL>(mcur, emap, elist, e0, nv, tid);
         if constexpr (FWD) load_x<S>(xcur, mcur, x);
     }
@@ -290,8 +254,6 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
             }
         int32_t mnext[NM];
         load_map<S, EL>(mnext, emap, elist, e0n, nvn, tid);
-        T dnext[kPrefetchD ? NS : 1][NC];
-        if constexpr (kPrefetchD) load_qdata<S, EL>(dnext, qd, elist, e0n, nvn, tid);
         lds_barrier();
         if constexpr (CENTRE && FWD) centre_tiles<S, E, NT>(bufA, emean, tid);
 
@@ -341,7 +303,6 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         }
 
         // D at quadrature points: v = D grad_ref u (symmetric 3x3) and/or v_u = D_m u
-        if constexpr (LOADD && kLateD) load_qdata<S, EL>(dq, qd, elist, e0, nv, tid);
 #pragma unroll
         for (int s = 0; s < (DSTEP ? NS : 0); ++s) {
             const int L = tid + s * NT;
@@ -371,16 +332,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
                 }
             }
         }
-        if (LOADD && more && !kLateD) {
-            if constexpr (kPrefetchD) {
-#pragma unroll
-                for (int s = 0; s < NS; ++s)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) dq[s][c] = dnext[s][c];
-            } else {
-                load_qdata<S, EL>(dq, qd, elist, e0n, nvn, tid);
-            }
-        }
+        if (LOADD && more) load_qdata<S, EL>(dq, qd, elist, e0n, nvn, tid);  // the next group's D
         lds_barrier();
 
         // transposed contractions and scatter-add
@@ -460,15 +412,8 @@ __global__ __launch_bounds__(256) void k_dstep(int64_t npts, const T *__restrict
 //   forward passes | wait, D-step | issue D(g+1) | transposed passes and scatter.
 // So the D stream of the next group overlaps the transposed passes and the forward
 // passes, and the gathers overlap the forward passes, without holding registers.
-#ifndef HEXPA_APPLY_DMA
-#define HEXPA_APPLY_DMA 2
-#endif
-#ifndef HEXPA_DMA_MIN_D
-#define HEXPA_DMA_MIN_D 6  // orders p >= 5 (measured faster there; p <= 4 keeps the register kernel)
-#endif
-#ifndef HEXPA_DMA_LDS_BUDGET
-#define HEXPA_DMA_LDS_BUDGET (53 * 1024)
-#endif
+constexpr int kDmaMinD = 6;                // orders p >= 5 (measured faster there; p <= 4 keeps the register kernel)
+constexpr int kDmaLdsBudget = 53 * 1024;   // LDS bytes per workgroup of the DMA kernel
 
 __device__ __forceinline__ uint32_t lds_byte_addr(const void *p)
 {
@@ -476,15 +421,6 @@ __device__ __forceinline__ uint32_t lds_byte_addr(const void *p)
 }
 // lane l writes [base + size l, base + size (l + 1)) of LDS; base is made wave-uniform.
 // M0 (the LDS base register of these loads) is saved and restored inside the statement.
-__device__ __forceinline__ void dma16(const void *src, uint32_t base)
-{
-    uint32_t saved;
-    asm volatile(
-        "s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
-        : "=&s"(saved)
-        : "v"(src), "s"(__builtin_amdgcn_readfirstlane(base))
-        : "memory");
-}
 __device__ __forceinline__ void dma4(const void *src, uint32_t base)
 {
     uint32_t saved;
@@ -496,22 +432,19 @@ __device__ __forceinline__ void dma4(const void *src, uint32_t base)
 }
 __device__ __forceinline__ void dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// HEXPA_APPLY_DMA 1: D staged in LDS too (where two elements still fit);
-//                 2: D in registers (loaded after the D-step for the next group).
+// D goes to registers (loaded after the D-step for the next group); the DOF map and the
+// gathered x go to LDS.
 template <int D, int Q, int OPS, class T>
 struct DmaShape {
     using B = Shape<D, Q, OPS, (int)sizeof(T)>;
     static constexpr int TB = (int)sizeof(T);
-    static constexpr bool DREG = HEXPA_APPLY_DMA == 2;
-    static constexpr int PER = TB * (B::SZ_A + B::SZ_B) + 12 * B::D3 + (TB == 8 ? 8 : 4) * B::D3 +
-                               (DREG ? 0 : TB * B::NCOMP * B::Q3);
+    static constexpr int PER = TB * (B::SZ_A + B::SZ_B) + 12 * B::D3 + (TB == 8 ? 8 : 4) * B::D3;
     // buffer tails for the padding columns of 16-column tiles (the exact bound; the smaller
     // footprint keeps four workgroups per CU for the 16-bit apply at p = 6)
     static constexpr int SLACK = 16 * cmax(B::DP, B::QP);
     static constexpr int FIXED = TB * 2 * SLACK + (int)sizeof(DevTables);
-    static constexpr int E = cclamp((HEXPA_DMA_LDS_BUDGET - FIXED) / PER, 1, 32);
-    static constexpr bool ok = HEXPA_APPLY_DMA != 0 && D >= HEXPA_DMA_MIN_D &&
-                               (DREG || (E >= 2 && (B::NCOMP * B::Q3 * TB) % 16 == 0));
+    static constexpr int E = cclamp((kDmaLdsBudget - FIXED) / PER, 1, 32);
+    static constexpr bool ok = D >= kDmaMinD;
 };
 
 template <int D, int Q, int OPS, int EX, bool ATOMIC>
@@ -524,19 +457,16 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
     using S = Shape<D, Q, OPS, (int)sizeof(T)>;
     constexpr int NT = kThreads;
     constexpr int E = DmaShape<D, Q, OPS, T>::E, D3 = S::D3, Q3 = S::Q3, NC = S::NCOMP, ED3 = E * D3;
-    constexpr bool DREG = DmaShape<D, Q, OPS, T>::DREG;
     constexpr int NSD = (E * Q3 + NT - 1) / NT;
-    constexpr int TPC = 16 / (int)sizeof(T), CPE = NC * Q3 / TPC, ECH = E * CPE;
     constexpr bool M = S::kMass, WIDE = sizeof(T) == 8;
     constexpr bool EL = !ATOMIC;  // only the coloured (plain read-modify-write) launches pass an element list
-    __shared__ T sD[DREG ? 1 : E * NC * Q3];
-    T dq[DREG ? NSD : 1][NC];
+    T dq[NSD][NC];
     __shared__ T bufA[E * S::SZ_A + DmaShape<D, Q, OPS, T>::SLACK];
     __shared__ T bufB[E * S::SZ_B + DmaShape<D, Q, OPS, T>::SLACK];
     __shared__ int32_t mapb[3][ED3];
     __shared__ uint32_t XL[ED3], XH[WIDE ? ED3 : 1];
     __shared__ DevTables stab;
-    constexpr bool CENTRE = HEXPA_LP_CENTRE && EX == EX_MFMA16B && OPS == 2;
+    constexpr bool CENTRE = EX == EX_MFMA16B && OPS == 2;
     __shared__ T emean[CENTRE ? E : 1];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -587,29 +517,17 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
             }
         }
     };
-    auto issue_d = [&](int gg) {
-        const int e0 = gg * E, nv = min(E, nelem - e0), nch = nv * CPE;
-        if constexpr (DREG) {  // into registers: slot s of thread tid is qp entry tid + s NT
+    auto issue_d = [&](int gg) {  // into registers: slot s of thread tid is qp entry tid + s NT
+        const int e0 = gg * E, nv = min(E, nelem - e0);
 #pragma unroll
-            for (int s = 0; s < NSD; ++s) {
-                const int L = tid + s * NT;
-                const int e = L / Q3, r = L - e * Q3;
-                const bool ok = e < nv;
-                const int64_t ge = ok ? (EL ? elist[e0 + e] : e0 + e) : 0;
-                const T *src = qd + ge * (int64_t)(NC * Q3) + r;
+        for (int s = 0; s < NSD; ++s) {
+            const int L = tid + s * NT;
+            const int e = L / Q3, r = L - e * Q3;
+            const bool ok = e < nv;
+            const int64_t ge = ok ? (EL ? elist[e0 + e] : e0 + e) : 0;
+            const T *src = qd + ge * (int64_t)(NC * Q3) + r;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) dq[s][c] = ok ? __builtin_nontemporal_load(src + c * Q3) : T(0);
-            }
-            return;
-        }
-        for (int c0 = wave * 64; c0 < ECH; c0 += NT) {
-            const int ch = c0 + lane;
-            const uint32_t base = lds_byte_addr(sD + c0 * TPC);
-            if (ch < nch) {
-                const int e = ch / CPE, w = ch - e * CPE;
-                const int64_t ge = EL ? elist[e0 + e] : e0 + e;
-                dma16(qd + ge * (int64_t)(NC * Q3) + w * TPC, base);
-            }
+            for (int c = 0; c < NC; ++c) dq[s][c] = ok ? __builtin_nontemporal_load(src + c * Q3) : T(0);
         }
     };
 
@@ -671,7 +589,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
                 T *V = bufB + e * S::SZ_B + Chan<Q, M>::qpos(r);
                 T dv[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) dv[c] = DREG ? dq[DREG ? s : 0][c] : sD[(e * NC + c) * Q3 + r];
+                for (int c = 0; c < NC; ++c) dv[c] = dq[s][c];
                 if constexpr (S::kDiff) {
                     using CH = Chan<Q, M>;
                     const T g0 = V[CH::X], g1 = V[CH::Y], g2 = V[CH::Z];
@@ -724,7 +642,6 @@ template <auto KERN>
 static int persistent_blocks(int nt, int ngroups)
 {
     const auto kern = KERN;
-    if (kOversub <= 0) return ngroups;
     static int cap = 0;
     if (cap == 0) {
         int per_cu = 0, dev = 0, ncu = 0;
@@ -732,7 +649,7 @@ static int persistent_blocks(int nt, int ngroups)
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
             ncu = 256;
-        cap = per_cu * ncu * kOversub;
+        cap = per_cu * ncu;
     }
     return ngroups < cap ? ngroups : cap;
 }

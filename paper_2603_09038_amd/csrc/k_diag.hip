@@ -21,7 +21,7 @@ namespace hexpa {
 
 namespace {
 
-constexpr int kDiagThreads = 256;
+constexpr int kDiagThreads = 512;
 
 // per-axis table index of each stored component (D order 00, 01, 02, 11, 12, 22, mass)
 enum : int { T_B2 = 0, T_BG = 1, T_G2 = 2 };
