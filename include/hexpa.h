@@ -322,6 +322,37 @@ int pa_lp_loss_grad(pa_lp *lp, const double *r, const double *t, double *loss, f
    NULL the call synchronises and stores L.  Asynchronous otherwise. */
 int pa_lp_train_step(pa_lp *lp, const double *b, const double *xstar, const double *xk, double *loss,
                      void *stream);
+/* Training over a set of systems (the epoch and draw loop of the training phase).  For
+   each epoch and each draw d: bind the handle to ops[d] (same box, order and essential
+   DOFs as the handle's operator: coefficient draws), form b = A_c x*_d, solve A_c x = b
+   from x = 0 to 1e-10 (or capture_at[n_capture-1] + 1 iterations) by FCG preconditioned
+   by the handle as it currently is (PA_LP_CAPTURE_FCG) or by FP64 Jacobi-PCG
+   (PA_LP_CAPTURE_JACOBI), recording the iterates x_k at k in capture_at, then run one
+   pa_lp_train_step per recorded iterate, in an order shuffled by a counter-based generator
+   seeded from (seed, epoch, draw).  Device buffers of size (n_capture + 2) ndof doubles are
+   allocated for the call.  The handle stays bound to the last operator.  Synchronous on
+   `stream`. */
+#define PA_LP_CAPTURE_FCG 0
+#define PA_LP_CAPTURE_JACOBI 1
+typedef struct {
+    int32_t ndraws;
+    int32_t capture;            /* PA_LP_CAPTURE_* */
+    pa_op *const *ops;          /* host [ndraws] operators (not owned) */
+    const double *const *xstar; /* host [ndraws] DEVICE pointers [ndof]: the known solutions */
+    const int32_t *capture_at;  /* host [n_capture] ascending iteration numbers >= 0 (0: x = 0) */
+    int32_t n_capture;
+    int32_t epochs;             /* passes over the draws, >= 1 */
+    uint32_t seed;
+    int32_t pad_;
+} pa_train_set;
+typedef struct {
+    int32_t steps;          /* training steps taken */
+    int32_t max_steps;      /* capacity of loss (0: losses not recorded) */
+    double *loss;           /* host [max_steps]: the loss of each step, in order */
+    double seconds_capture; /* wall time of binding, right-hand sides and capture solves */
+    double seconds_train;   /* wall time of the training steps */
+} pa_train_log;
+int pa_lp_train(pa_lp *lp, const pa_train_set *set, pa_train_log *log, void *stream);
 /* Parameters to/from a file: magic "HEXPALP1", int32 version 1, int32 count, the FP32
    values, and a 64-bit FNV-1a checksum of them.  PA_ERR_IO on any mismatch. */
 int pa_lp_save(pa_lp *lp, const char *path);

@@ -1,6 +1,7 @@
 // C-ABI of the learned two-level preconditioner: handle lifetime, binding to an operator
 // (coarse p=1 operator and its probed stencil, log-kappa tiles, multiplicities),
 // application z = M(r), loss/gradient, Adam training step and parameter files.
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -518,6 +519,100 @@ extern "C" int pa_lp_train_step(pa_lp *lp, const double *b, const double *xstar,
     if (loss) {
         HIP_OK(hipMemcpyAsync(loss, lp->dsc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
+    }
+    return PA_OK;
+    PA_CATCH
+}
+
+namespace {
+// splitmix64 (Steele, Lea & Flood 2014): the pair order of each (epoch, draw) is a
+// Fisher-Yates shuffle driven by this counter-based generator
+uint64_t splitmix64(uint64_t &state)
+{
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+}  // namespace
+
+extern "C" int pa_lp_train(pa_lp *lp, const pa_train_set *set, pa_train_log *log, void *stream)
+{
+    PA_TRY
+    if (!lp || !set || !log) return arg_error("pa_lp_train: NULL argument");
+    if (set->ndraws < 0 || (set->ndraws > 0 && (!set->ops || !set->xstar)))
+        return arg_error("pa_lp_train: ndraws < 0, or ops / xstar missing");
+    if (set->capture != PA_LP_CAPTURE_FCG && set->capture != PA_LP_CAPTURE_JACOBI)
+        return arg_error("pa_lp_train: unknown capture mode");
+    if (set->n_capture < 1 || !set->capture_at) return arg_error("pa_lp_train: need n_capture >= 1 and capture_at");
+    for (int j = 0; j < set->n_capture; ++j)
+        if (set->capture_at[j] < 0 || (j > 0 && set->capture_at[j] <= set->capture_at[j - 1]))
+            return arg_error("pa_lp_train: capture_at must be ascending and >= 0");
+    if (set->epochs < 1) return arg_error("pa_lp_train: epochs must be >= 1");
+    if (log->max_steps < 0 || (log->max_steps > 0 && !log->loss))
+        return arg_error("pa_lp_train: log->loss is NULL with max_steps > 0");
+    for (int d = 0; d < set->ndraws; ++d)
+        if (!set->ops[d] || !set->xstar[d]) return arg_error("pa_lp_train: NULL operator or solution");
+    log->steps = 0;
+    log->seconds_capture = log->seconds_train = 0.0;
+    if (set->ndraws == 0) return PA_OK;
+    hipStream_t s = as_stream(stream);
+    const int64_t nd = set->ops[0]->ndof;
+    const int ncap = set->n_capture;
+    double *b = nullptr, *x = nullptr, *cap = nullptr;
+    HIP_OK(dalloc(&b, (size_t)nd));
+    std::unique_ptr<void, void (*)(void *)> g1(b, dfree);
+    HIP_OK(dalloc(&x, (size_t)nd));
+    std::unique_ptr<void, void (*)(void *)> g2(x, dfree);
+    HIP_OK(dalloc(&cap, (size_t)nd * ncap));
+    std::unique_ptr<void, void (*)(void *)> g3(cap, dfree);
+    std::vector<int> order;
+    for (int ep = 0; ep < set->epochs; ++ep) {
+        for (int d = 0; d < set->ndraws; ++d) {
+            pa_op *op = set->ops[d];
+            if (op->ndof != nd) return arg_error("pa_lp_train: the operators differ in size");
+            auto t0 = std::chrono::steady_clock::now();
+            int rc = (lp->op == op) ? PA_OK : pa_lp_bind(lp, op);
+            if (rc) return rc;
+            // b = A_c x*, then the iterates of the capture solve from x = 0
+            rc = do_apply_constrained(op, set->xstar[d], b, s);
+            if (rc) return rc;
+            HIP_OK(vec_fill(x, 0.0, nd, s));
+            pa_cg_opts o;
+            std::memset(&o, 0, sizeof(o));
+            o.rtol = 1e-10;
+            o.max_it = set->capture_at[ncap - 1] + 1;
+            o.mode = set->capture == PA_LP_CAPTURE_FCG ? PA_CG_FCG : PA_CG_JACOBI;
+            o.check_every = 8;
+            o.constrained = 1;
+            o.lp = set->capture == PA_LP_CAPTURE_FCG ? lp : nullptr;
+            o.n_capture = ncap;
+            o.capture_at = set->capture_at;
+            o.capture_x = cap;
+            pa_cg_result res;
+            rc = cg_solve(op, b, x, &o, &res, stream);
+            if (rc != PA_OK && rc != PA_ERR_NOT_CONVERGED) return rc;
+            int reached = 0;
+            while (reached < ncap && set->capture_at[reached] <= res.iters) ++reached;
+            auto t1 = std::chrono::steady_clock::now();
+            // one training step per captured pair, in a seeded random order
+            order.resize(reached);
+            for (int j = 0; j < reached; ++j) order[j] = j;
+            uint64_t st = ((uint64_t)set->seed << 32) ^ ((uint64_t)ep << 20) ^ (uint64_t)d;
+            for (int j = reached - 1; j > 0; --j) std::swap(order[j], order[(int)(splitmix64(st) % (uint64_t)(j + 1))]);
+            for (int j : order) {
+                double L = 0.0;
+                const bool keep = log->steps < log->max_steps;
+                rc = pa_lp_train_step(lp, b, set->xstar[d], cap + (size_t)j * nd, keep ? &L : nullptr, stream);
+                if (rc) return rc;
+                if (keep) log->loss[log->steps] = L;
+                log->steps += 1;
+            }
+            HIP_OK(hipStreamSynchronize(s));
+            auto t2 = std::chrono::steady_clock::now();
+            log->seconds_capture += std::chrono::duration<double>(t1 - t0).count();
+            log->seconds_train += std::chrono::duration<double>(t2 - t1).count();
+        }
     }
     return PA_OK;
     PA_CATCH

@@ -24,6 +24,7 @@ PA_VARIANT_MFMA_MF, PA_VARIANT_VALU_MF = 5, 6
 PA_CG_PLAIN, PA_CG_JACOBI, PA_CG_MIXED_IR, PA_CG_FCG, PA_CG_MIXED_FCG, PA_CG_MIXED_RU = 0, 1, 2, 3, 4, 5
 PA_LP_LOSS_ENERGY, PA_LP_LOSS_L2 = 0, 1
 PA_LP_FP16, PA_LP_BF16 = 0, 1
+PA_LP_CAPTURE_FCG, PA_LP_CAPTURE_JACOBI = 0, 1
 
 # every symbol include/hexpa.h declares
 EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_lp", "pa_apply_unfused_noalloc", "pa_apply_constrained", "pa_diag", "pa_load", "pa_qpoints", "pa_nodes",
@@ -31,7 +32,7 @@ EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_lp", "pa_apply_unfu
            "cg_solve", "pa_debug_mfma_f64", "pa_debug_mfma16",
            "pa_lp_create", "pa_lp_bind", "pa_lp_configure", "pa_lp_num_params", "pa_lp_get_params",
            "pa_lp_set_params", "pa_lp_logk", "pa_lp_apply", "pa_lp_coarse", "pa_lp_net", "pa_lp_loss_grad",
-           "pa_lp_train_step", "pa_lp_save", "pa_lp_load", "pa_lp_destroy")
+           "pa_lp_train_step", "pa_lp_train", "pa_lp_save", "pa_lp_load", "pa_lp_destroy")
 
 
 class HexpaError(RuntimeError):
@@ -79,6 +80,17 @@ class LpOpts(ctypes.Structure):
                 ("lr", ctypes.c_double), ("net_scale", ctypes.c_double)]
 
 
+class TrainSet(ctypes.Structure):
+    _fields_ = [("ndraws", ctypes.c_int32), ("capture", ctypes.c_int32), ("ops", ctypes.c_void_p),
+                ("xstar", ctypes.c_void_p), ("capture_at", ctypes.c_void_p), ("n_capture", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("seed", ctypes.c_uint32), ("pad_", ctypes.c_int32)]
+
+
+class TrainLog(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("max_steps", ctypes.c_int32), ("loss", ctypes.c_void_p),
+                ("seconds_capture", ctypes.c_double), ("seconds_train", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
@@ -117,6 +129,7 @@ def _load():
         "pa_lp_net": [vp, vp, vp, vp],
         "pa_lp_loss_grad": [vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp],
         "pa_lp_train_step": [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp],
+        "pa_lp_train": [vp, ctypes.POINTER(TrainSet), ctypes.POINTER(TrainLog), vp],
         "pa_lp_save": [vp, ctypes.c_char_p],
         "pa_lp_load": [vp, ctypes.c_char_p],
     }
@@ -366,6 +379,22 @@ def pa_lp_train_step(lp, b, xstar, xk, want_loss=True, stream=None):
     return loss.value if want_loss else None
 
 
+def pa_lp_train(lp, ops, xstars, capture_at, capture=PA_LP_CAPTURE_FCG, epochs=1, seed=0, max_steps=100000,
+                stream=None):
+    """ops: pa_op handles; xstars: device FP64 tensors [ndof], one per operator.  Returns
+    (losses, seconds_capture, seconds_train)."""
+    n = len(ops)
+    opv = (ctypes.c_void_p * max(n, 1))(*[o.value if isinstance(o, ctypes.c_void_p) else o for o in ops])
+    xv = (ctypes.c_void_p * max(n, 1))(*[_dptr(x).value for x in xstars])
+    cat = np.ascontiguousarray(capture_at, dtype=np.int32)
+    ts = TrainSet(n, int(capture), ctypes.cast(opv, ctypes.c_void_p), ctypes.cast(xv, ctypes.c_void_p),
+                  cat.ctypes.data, cat.size, int(epochs), int(seed) & 0xFFFFFFFF, 0)
+    loss = np.zeros(max(int(max_steps), 1))
+    tl = TrainLog(0, int(max_steps), loss.ctypes.data, 0.0, 0.0)
+    _check(_lib.pa_lp_train(lp, ctypes.byref(ts), ctypes.byref(tl), _stream(stream)))
+    return loss[:min(tl.steps, int(max_steps))].copy(), tl.seconds_capture, tl.seconds_train
+
+
 def pa_lp_save(lp, path):
     _check(_lib.pa_lp_save(lp, os.fsencode(path)))
 
@@ -509,6 +538,11 @@ class LearnedPreconditioner:
 
     def train_step(self, b, xstar, xk, want_loss=True):
         return pa_lp_train_step(self.h, b, xstar, xk, want_loss)
+
+    def train(self, ops, xstars, capture_at, capture=PA_LP_CAPTURE_FCG, epochs=1, seed=0):
+        losses, tc, tt = pa_lp_train(self.h, [o.h for o in ops], xstars, capture_at, capture, epochs, seed)
+        self.op = ops[-1] if ops else self.op
+        return losses, tc, tt
 
     def save(self, path):
         pa_lp_save(self.h, path)

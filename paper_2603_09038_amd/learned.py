@@ -54,34 +54,40 @@ def capture_iterates(op, xstar, lp=None, max_it=None, capture_at=None):
     return b, cap[reached], res
 
 
-def train(lp, mesh, n, p, draws, epochs=1, seed=0, sigma=1.0, log=None, capture="fcg", nfft=128):
-    """Train lp's network on the iterates of the given coefficient draws (one operator
-    at a time): iterates of FCG with the preconditioner as it currently is (capture
-    "fcg"; the untrained network adds nothing, so the first pass sees the two-level
-    method without it) or of Jacobi-PCG ("jacobi").  Returns per-step losses and the
-    seconds spent (capture and training)."""
+def train(lp, mesh, n, p, draws, epochs=1, seed=0, sigma=1.0, log=None, capture="fcg", nfft=128, chunk=50):
+    """Train lp's network on the iterates of the given coefficient draws: the library's
+    pa_lp_train runs the capture solves (FCG with the preconditioner as it currently is,
+    capture "fcg" -- the untrained network adds nothing, so the first pass sees the
+    two-level method without it -- or Jacobi-PCG, "jacobi") and the training steps.  This
+    function only builds the operators of `chunk` draws at a time (bounding device
+    memory) and hands them over.  Returns per-step losses and the seconds spent (building
+    the operators and capturing; training)."""
     import synth
     import torch
-    rng = np.random.default_rng([seed, 11])
     losses, t_capture, t_train = [], 0.0, 0.0
+    at = CAPTURE_AT_FCG if capture == "fcg" else CAPTURE_AT
+    mode = hexpa.PA_LP_CAPTURE_FCG if capture == "fcg" else hexpa.PA_LP_CAPTURE_JACOBI
     for ep in range(epochs):
-        for d in draws:
+        for c0 in range(0, len(draws), chunk):
             t0 = time.perf_counter()
-            op = lognormal_operator(mesh, n, p, d, sigma=sigma, nfft=nfft)
-            xstar = torch.tensor(synth.train_solution(op.nodes().cpu().numpy(), d), dtype=torch.float64,
-                                 device="cuda")
-            lp.bind(op)
-            b, xs, _ = capture_iterates(op, xstar, lp=lp if capture == "fcg" else None)
+            ops, xs = [], []
+            for d in draws[c0:c0 + chunk]:
+                op = lognormal_operator(mesh, n, p, d, sigma=sigma, nfft=nfft)
+                ops.append(op)
+                xs.append(torch.tensor(synth.train_solution(op.nodes().cpu().numpy(), d), dtype=torch.float64,
+                                       device="cuda"))
             torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for j in rng.permutation(xs.shape[0]):
-                losses.append(lp.train_step(b, xstar, xs[j]))
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            t_capture += t1 - t0
-            t_train += t2 - t1
+            t_build = time.perf_counter() - t0
+            ls, tc, tt = lp.train(ops, xs, at, capture=mode, epochs=1, seed=seed * 1000003 + ep * 1009 + c0)
+            losses.extend(ls.tolist())
+            t_capture += t_build + tc
+            t_train += tt
             if log:
-                log(f"epoch {ep} draw {d}: {xs.shape[0]} pairs, mean loss {np.mean(losses[-xs.shape[0]:]):.4f}")
+                log(f"epoch {ep} draws {draws[c0]}..{draws[min(c0 + chunk, len(draws)) - 1]}: {len(ls)} steps, "
+                    f"mean loss {np.mean(ls):.4f}")
+            del xs
+            for op in ops[:-1]:  # lp keeps the last one, to which the handle stays bound
+                op.close()
     return losses, t_capture, t_train
 
 

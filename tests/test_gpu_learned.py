@@ -286,3 +286,43 @@ def test_training_reduces_fcg_iterations(hx):
     assert r["coarse_net"]["iters"] < r["coarse_jacobi"]["iters"] < r["jacobi"]["iters"]
     lp.close()
 
+
+
+def test_pa_lp_train_matches_the_step_by_step_loop(hx):
+    """pa_lp_train over two draws with one captured iterate each (so the pair order is
+    fixed) against the same steps taken one call at a time: bind, b = A_c x*, Jacobi-PCG
+    with iterate capture, one training step."""
+    import torch
+    from paper_2603_09038_amd import learned
+    n, p = 4, 2
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    ops = [learned.lognormal_operator(mesh, n, p, d, nfft=32) for d in (3, 4)]
+    xs = [torch.tensor(synth.train_solution(o.nodes().cpu().numpy(), d, nfft=32), dtype=torch.float64, device="cuda")
+          for o, d in zip(ops, (3, 4))]
+    ps = synth.flat_params(synth.net_params(2, 16, seed=50))
+    at = [5]
+    lp1 = hx.LearnedPreconditioner(ops[0], use_net=True, use_coarse=True, coarse_iters=4, lr=1e-3)
+    lp1.set_params(ps)
+    losses, tc, tt = lp1.train(ops, xs, at, capture=hx.PA_LP_CAPTURE_JACOBI)
+    assert losses.size == 2 and np.all(np.isfinite(losses))
+    lp2 = hx.LearnedPreconditioner(ops[0], use_net=True, use_coarse=True, coarse_iters=4, lr=1e-3)
+    lp2.set_params(ps)
+    ref = []
+    for o, x in zip(ops, xs):
+        lp2.bind(o)
+        b = o.apply_constrained(x)
+        cap = torch.empty((1, o.ndof), dtype=torch.float64, device="cuda")
+        xk = torch.zeros_like(b)
+        hx.cg_solve(o.h, b, xk, rtol=1e-10, max_it=at[-1] + 1, mode=hx.PA_CG_JACOBI, capture_at=at, capture_x=cap,
+                    check_every=8, raise_on_fail=False)
+        ref.append(lp2.train_step(b, x, cap[0]))
+    np.testing.assert_allclose(losses, ref, rtol=1e-6)
+    p1, p2 = lp1.params(), lp2.params()
+    assert np.linalg.norm(p1 - p2) <= 1e-5 * np.linalg.norm(p2)
+    assert not np.array_equal(p1, ps)  # training moved the parameters
+    with pytest.raises(hx.HexpaError):
+        hx.pa_lp_train(lp1.h, [o.h for o in ops], xs, [3, 2])  # capture_at not ascending
+    lp1.close()
+    lp2.close()
+    for o in ops:
+        o.close()
