@@ -113,7 +113,6 @@ extern "C" void pa_destroy(pa_op *op)
 {
     if (!op) return;
     dfree(op->d_elem_dofs);
-    dfree(op->d_smap);
     dfree(op->d_qdata);
     dfree(op->d_qdata32);
     dfree(op->d_qbuf);
@@ -245,16 +244,6 @@ extern "C" int pa_setup(const pa_mesh_desc *m, int order, int q1d, const pa_coef
     HIP_OK(dalloc(&op->d_scratch, (size_t)op->ndof));
     op->scratch_len = (size_t)op->ndof;
     HIP_OK(hipMemcpy(op->d_elem_dofs, ed.data(), ed.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    {
-        // scatter map: DOFs touched by one element only are written without atomics
-        std::vector<uint8_t> mult((size_t)op->ndof, 0);
-        for (int32_t v : ed)
-            if (mult[(size_t)v] < 2) ++mult[(size_t)v];
-        std::vector<int32_t> sm(ed.size());
-        for (size_t i = 0; i < ed.size(); ++i) sm[i] = mult[(size_t)ed[i]] == 1 ? -ed[i] - 2 : ed[i];
-        HIP_OK(dalloc(&op->d_smap, sm.size()));
-        HIP_OK(hipMemcpy(op->d_smap, sm.data(), sm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
     HIP_OK(hipMemcpy(op->d_vert, m->vert_xyz, (size_t)m->nvert * 3 * sizeof(double), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(op->d_hex, m->hex, (size_t)nel * 8 * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(op->d_tab, &ht, sizeof(ht), hipMemcpyHostToDevice));

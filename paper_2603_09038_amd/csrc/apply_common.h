@@ -125,27 +125,19 @@ struct LdsOut {
     int sz;
     __device__ __forceinline__ void put(int e, int addr, T v) const { out[e * sz + addr] = v; }
 };
-// Scatter-map entries (the DOF map as the apply kernels read it): m >= 0 is a DOF that
-// other elements share (atomic add), m <= -2 is DOF -m - 2 that only this element touches
-// (every element-interior node of a conforming mesh): a plain read-modify-write, with no
-// atomic traffic; -1 marks an absent element slot.
-__device__ __forceinline__ int smap_dof(int m) { return m >= 0 ? m : -m - 2; }
-
 template <bool ATOMIC, class T>
 struct GlobalOut {
     T *y;
-    const int32_t *lmap;  // [E][D^3] scatter-map entry per local node
+    const int32_t *lmap;  // [E][D^3] global index per local node, -1 for absent elements
     int d3;
     __device__ __forceinline__ void put(int e, int addr, T v) const
     {
-        const int m = lmap[e * d3 + addr];
-        if (m >= 0) {
+        const int g = lmap[e * d3 + addr];
+        if (g >= 0) {
             if (ATOMIC)
-                unsafeAtomicAdd(y + m, v);
+                unsafeAtomicAdd(y + g, v);
             else
-                y[m] += v;
-        } else if (m != -1) {
-            y[-m - 2] += v;
+                y[g] += v;
         }
     }
 };

@@ -51,8 +51,6 @@ struct pa_op {
     int grid_cap = 0;                // > 0: at most this many workgroups per apply launch (pa_set_grid_cap)
     int device = 0;
     int32_t *d_elem_dofs = nullptr;  // [nelem][d^3]
-    int32_t *d_smap = nullptr;       // [nelem][d^3] scatter map of the apply kernels: the DOF, or -DOF-2
-                                     // where no other element touches it
     double *d_qdata = nullptr;       // [nelem][ncomp][q^3]
     float *d_qdata32 = nullptr;      // FP32 copy of D for the mixed-precision apply (lazy)
     double *d_qbuf = nullptr;        // quadrature-point tensor of the unfused apply (lazy)

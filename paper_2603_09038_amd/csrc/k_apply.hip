@@ -130,7 +130,7 @@ __device__ __forceinline__ void load_x(T (&xv)[GroupRegs<S>::NM], const int32_t 
                                        const T *__restrict__ x)
 {
 #pragma unroll
-    for (int s = 0; s < GroupRegs<S>::NM; ++s) xv[s] = m[s] != -1 ? x[smap_dof(m[s])] : T(0);
+    for (int s = 0; s < GroupRegs<S>::NM; ++s) xv[s] = m[s] >= 0 ? x[m[s]] : T(0);
 }
 
 // One contraction pass with the chosen executor.  MFMA A-operands are read from the LDS
@@ -511,7 +511,7 @@ __global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
             const uint32_t bh = WIDE ? lds_byte_addr(&XH[L0]) : 0u;
             if (L < ED3) {
                 const int m = mapb[b][L];
-                const T *src = x + (m != -1 ? smap_dof(m) : 0);
+                const T *src = x + (m >= 0 ? m : 0);
                 dma4(src, bl);
                 if constexpr (WIDE) dma4(reinterpret_cast<const char *>(src) + 4, bh);
             }
@@ -672,14 +672,14 @@ static hipError_t launch_unfused(const pa_op *op, const double *x, double *y, do
     constexpr auto k1 = k_apply<D, Q, OPS, EX, true, 1>;
     constexpr auto k3 = k_apply<D, Q, OPS, EX, true, 2>;
     hipLaunchKernelGGL(k1, dim3(capped(op, persistent_blocks<k1>(CFG::NT, ngroups))), dim3(CFG::NT), 0, s, n, ngroups,
-                       (const int32_t *)nullptr, op->d_smap, op->d_qdata, op->d_tab, x, y, qbuf, op->d_vert,
+                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf, op->d_vert,
                        op->d_hex, op->coeff);
     const int64_t npts = (int64_t)n * S::Q3;
     auto k2 = k_dstep<Q, OPS, double>;
     hipLaunchKernelGGL(k2, dim3((unsigned)std::min<int64_t>((npts + 255) / 256, 65536)), dim3(256), 0, s, npts,
                        (const double *)op->d_qdata, qbuf);
     hipLaunchKernelGGL(k3, dim3(capped(op, persistent_blocks<k3>(CFG::NT, ngroups))), dim3(CFG::NT), 0, s, n, ngroups,
-                       (const int32_t *)nullptr, op->d_smap, op->d_qdata, op->d_tab, x, y, qbuf, op->d_vert,
+                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, qbuf, op->d_vert,
                        op->d_hex, op->coeff);
     return hipGetLastError();
 }
@@ -695,7 +695,7 @@ static hipError_t launch_mf(const pa_op *op, const double *x, double *y, hipStre
     if (ngroups == 0) return hipSuccess;
     constexpr auto k = k_apply<D, Q, OPS, EX, true, 3>;
     hipLaunchKernelGGL(k, dim3(capped(op, persistent_blocks<k>(CFG::NT, ngroups))), dim3(CFG::NT), 0, s, n, ngroups,
-                       (const int32_t *)nullptr, op->d_smap, op->d_qdata, op->d_tab, x, y, (double *)nullptr,
+                       (const int32_t *)nullptr, op->d_elem_dofs, op->d_qdata, op->d_tab, x, y, (double *)nullptr,
                        op->d_vert, op->d_hex, op->coeff);
     return hipGetLastError();
 }
@@ -715,12 +715,12 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
     if constexpr (!DMA) {
         constexpr auto kern = k_apply<D, Q, OPS, EX, ATOMIC, 0>;
         const int nblocks = capped(op, persistent_blocks<kern>(NT, ngroups));
-        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_smap, qd, op->d_tab, x,
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab, x,
                            y, (T *)nullptr, (const double *)nullptr, (const int32_t *)nullptr, CoeffDev{});
     } else {
         constexpr auto kern = k_apply_dma<D, Q, OPS, EX, ATOMIC>;
         const int nblocks = capped(op, persistent_blocks<kern>(NT, ngroups));
-        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_smap, qd, op->d_tab, x,
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(NT), 0, s, n, ngroups, elist, op->d_elem_dofs, qd, op->d_tab, x,
                            y);
     }
     return hipGetLastError();
