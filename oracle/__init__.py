@@ -229,3 +229,78 @@ class Assembled:
         lib().orc_apply_assembled(ctypes.c_int64(self.prob.nelem), ctypes.c_int(self.prob.nd), _p(self.Ae),
                                   _p(self.prob.elem_dofs), ctypes.c_int64(self.ndof), _p(_f64(x)), _p(y))
         return y
+
+
+class MixedProblem:
+    """The off-diagonal blocks of the acoustic block operator (the paper's eq. (4)) on a
+    mesh: pressure in the continuous order-p space (GLL nodes), velocity in the
+    discontinuous order-pu space (Lagrange on pu+1 Gauss-Legendre points per axis, three
+    scalar components, element-local vectors [nelem][3][(pu+1)^3]), q-point Gauss rule.
+    G p = (grad p, tau) and -G^T u = -(u, grad v); lumped masses by row sums."""
+
+    def __init__(self, mesh, p=4, pu=3, q=5, rho=1.0, bulk=1.0):
+        self.mesh, self.p, self.pu, self.q = mesh, int(p), int(pu), int(q)
+        self.rho, self.bulk = float(rho), float(bulk)
+        self.vert = _f64(mesh["vert"])
+        self.hex = _i32(mesh["hex"])
+        self.nelem = self.hex.shape[0]
+        self.nd = (self.p + 1) ** 3
+        self.nu = (self.pu + 1) ** 3
+        self.elem_dofs = _i32(box_elem_dofs(mesh["n"], self.p))
+        self.ndof = int(self.elem_dofs.max()) + 1
+        self.nvel = self.nelem * 3 * self.nu
+
+    def elem_matrices(self, subset=None):
+        sub = None if subset is None else _i32(subset)
+        ns = self.nelem if sub is None else sub.size
+        Ge = np.zeros((ns, 3 * self.nu, self.nd))
+        if lib().orc_mixed_elem_matrices(ctypes.c_int64(ns), None if sub is None else _p(sub), _p(self.vert),
+                                         _p(self.hex), ctypes.c_int(self.p), ctypes.c_int(self.pu),
+                                         ctypes.c_int(self.q), _p(Ge)):
+            raise RuntimeError("orc_mixed_elem_matrices failed")
+        return Ge
+
+    def apply(self, u, pv):
+        """(yu, yp) = (G p, -G^T u)."""
+        u, pv = _f64(u).ravel(), _f64(pv)
+        yu = np.zeros(self.nvel)
+        yp = np.zeros(self.ndof)
+        if lib().orc_mixed_apply(ctypes.c_int64(self.nelem), _p(self.vert), _p(self.hex), _p(self.elem_dofs),
+                                 ctypes.c_int(self.p), ctypes.c_int(self.pu), ctypes.c_int(self.q),
+                                 ctypes.c_int64(self.ndof), _p(u), _p(pv), _p(yu), _p(yp)):
+            raise RuntimeError("orc_mixed_apply failed")
+        return yu, yp
+
+    def lumped(self):
+        """(mu [nelem][nu], mp [ndof]): velocity mass rows (one per node, the same for each
+        component) and the assembled pressure mass rows."""
+        mu = np.zeros(self.nelem * self.nu)
+        mp = np.zeros(self.ndof)
+        if lib().orc_mixed_lumped(ctypes.c_int64(self.nelem), _p(self.vert), _p(self.hex), _p(self.elem_dofs),
+                                  ctypes.c_int(self.p), ctypes.c_int(self.pu), ctypes.c_int(self.q),
+                                  ctypes.c_double(self.rho), ctypes.c_double(self.bulk), ctypes.c_int64(self.ndof),
+                                  _p(mu), _p(mp)):
+            raise RuntimeError("orc_mixed_lumped failed")
+        return mu, mp
+
+    def velocity_mass_rows(self):
+        """mu expanded to the velocity layout [nelem][3][nu]."""
+        mu, _ = self.lumped()
+        return np.repeat(mu.reshape(self.nelem, 1, self.nu), 3, axis=1).ravel()
+
+    def rhs(self, u, pv, mu3=None, mp=None):
+        """Time derivative of the semi-discrete system M [u; p]' = -A [u; p] with the
+        off-diagonal blocks of eq. (4) (no boundary terms: u . n = 0 on the box):
+        u' = -Mu^{-1} G p, p' = Mp^{-1} G^T u."""
+        if mu3 is None:
+            mu3 = self.velocity_mass_rows()
+        if mp is None:
+            _, mp = self.lumped()
+        yu, yp = self.apply(u, pv)
+        return -yu / mu3, -yp / mp
+
+    def rk4(self, u, pv, dt, nsteps):
+        from .solvers import rk4
+        mu3 = self.velocity_mass_rows()
+        _, mp = self.lumped()
+        return rk4(lambda a, b: self.rhs(a, b, mu3, mp), _f64(u).ravel().copy(), _f64(pv).copy(), dt, nsteps)

@@ -1,5 +1,6 @@
 /*
- * CPU FP64 oracle for the H1 mass and diffusion operators on trilinear hexahedra.
+ * CPU FP64 oracle for the H1 mass and diffusion operators on trilinear hexahedra, and
+ * for the mixed H1 x L2 gradient / divergence blocks of the acoustic operator (eq. (4)).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
  * includes this file; only the test-suite, the smoke check and the CPU-baseline
@@ -558,6 +559,173 @@ int orc_load(int64_t nelem, const double *vert, const int32_t *hex, const int32_
     for (int64_t e = 0; e < nelem; ++e)
         for (int I = 0; I < nd; ++I) b[elem_dofs[e * nd + I]] += bE[e * nd + I];
     free(bE);
+    tables_free(&T);
+    return 0;
+}
+
+/* ------------------------------------------- mixed H1 x L2 gradient block (acoustic operator)
+
+   The off-diagonal blocks of the paper's block operator, eq. (4), for pressure p in the
+   continuous order-p space (GLL nodes, global DOF map) and velocity u in the discontinuous
+   order-pu space (Lagrange on the pu+1 Gauss-Legendre points per axis, element-local,
+   three scalar components): with psi_J the velocity basis and phi_I the pressure basis,
+
+       G_e[(c, J)][I] = (d phi_I / d x_c, psi_J)_e = sum_q w_q detJ_q psi_J(x_q) (J^{-T} grad_ref phi_I)_c
+
+   so that (grad p, tau) = G p and -(u, grad v) = -G^T u.  The element matrices are built by
+   plain quadrature loops with physical gradients (no sum factorization).  Velocity vectors
+   are [nelem][3][nu], nu = (pu+1)^3, local node J = j1 + du (j2 + du j3), du = pu + 1. */
+
+typedef struct {
+    int du, nu;
+    double nodes[64];
+    double *L; /* [q][du] velocity basis values at the Gauss points */
+} utables;
+
+static int utables_init(utables *U, int pu, int q, const double *qx)
+{
+    double w[64];
+    U->du = pu + 1;
+    U->nu = U->du * U->du * U->du;
+    if (orc_gauss(U->du, U->nodes, w)) return -1;
+    U->L = (double *)malloc(sizeof(double) * q * U->du);
+    for (int a = 0; a < q; ++a) orc_lagrange(U->du, U->nodes, qx[a], U->L + a * U->du, NULL);
+    return 0;
+}
+
+static void mixed_elem(const tables *T, const utables *U, const double X[24], double *Ge, double *phi, double *gphi)
+{
+    const int nd = T->nd, nu = U->nu, du = U->du, q = T->q;
+    memset(Ge, 0, sizeof(double) * 3 * nu * nd);
+    for (int c = 0; c < q; ++c)
+        for (int b = 0; b < q; ++b)
+            for (int a = 0; a < q; ++a) {
+                double x[3];
+                double wdet = basis_at_qp(T, X, a, b, c, phi, gphi, x, NULL);
+                for (int j3 = 0; j3 < du; ++j3)
+                    for (int j2 = 0; j2 < du; ++j2)
+                        for (int j1 = 0; j1 < du; ++j1) {
+                            int J = j1 + du * (j2 + du * j3);
+                            double psi = U->L[a * du + j1] * U->L[b * du + j2] * U->L[c * du + j3];
+                            for (int comp = 0; comp < 3; ++comp) {
+                                double *row = Ge + (int64_t)(comp * nu + J) * nd;
+                                for (int I = 0; I < nd; ++I) row[I] += wdet * psi * gphi[3 * I + comp];
+                            }
+                        }
+            }
+}
+
+/* Element matrices G_e [nsel][3 nu][nd] of the listed elements (all if subset == NULL). */
+int orc_mixed_elem_matrices(int64_t nsel, const int32_t *subset, const double *vert, const int32_t *hex,
+                            int p, int pu, int q, double *Ge_out)
+{
+    tables T;
+    utables U;
+    if (tables_init(&T, p, q)) return -1;
+    if (utables_init(&U, pu, q, T.qx)) { tables_free(&T); return -1; }
+    const int nd = T.nd, nu = U.nu;
+#pragma omp parallel
+    {
+        double *phi = (double *)malloc(sizeof(double) * nd);
+        double *gphi = (double *)malloc(sizeof(double) * 3 * nd);
+#pragma omp for schedule(dynamic, 2)
+        for (int64_t s = 0; s < nsel; ++s) {
+            int64_t e = subset ? subset[s] : s;
+            double X[24];
+            gather_corners(vert, hex, e, X);
+            mixed_elem(&T, &U, X, Ge_out + s * (int64_t)3 * nu * nd, phi, gphi);
+        }
+        free(phi); free(gphi);
+    }
+    free(U.L);
+    tables_free(&T);
+    return 0;
+}
+
+/* yu = G p (element-local velocity space) and yp = -G^T u (global pressure vector). */
+int orc_mixed_apply(int64_t nelem, const double *vert, const int32_t *hex, const int32_t *elem_dofs, int p, int pu,
+                    int q, int64_t ndof, const double *u, const double *pv, double *yu, double *yp)
+{
+    tables T;
+    utables U;
+    if (tables_init(&T, p, q)) return -1;
+    if (utables_init(&U, pu, q, T.qx)) { tables_free(&T); return -1; }
+    const int nd = T.nd, nu = U.nu;
+    double *ypE = (double *)malloc(sizeof(double) * nelem * nd);
+#pragma omp parallel
+    {
+        double *phi = (double *)malloc(sizeof(double) * nd);
+        double *gphi = (double *)malloc(sizeof(double) * 3 * nd);
+        double *Ge = (double *)malloc(sizeof(double) * 3 * nu * nd);
+#pragma omp for schedule(dynamic, 2)
+        for (int64_t e = 0; e < nelem; ++e) {
+            double X[24];
+            gather_corners(vert, hex, e, X);
+            mixed_elem(&T, &U, X, Ge, phi, gphi);
+            const int32_t *g = elem_dofs + e * nd;
+            for (int r = 0; r < 3 * nu; ++r) {
+                double acc = 0.0;
+                for (int I = 0; I < nd; ++I) acc += Ge[(int64_t)r * nd + I] * pv[g[I]];
+                yu[e * 3 * nu + r] = acc;
+            }
+            for (int I = 0; I < nd; ++I) {
+                double acc = 0.0;
+                for (int r = 0; r < 3 * nu; ++r) acc += Ge[(int64_t)r * nd + I] * u[e * 3 * nu + r];
+                ypE[e * nd + I] = -acc;
+            }
+        }
+        free(phi); free(gphi); free(Ge);
+    }
+    memset(yp, 0, sizeof(double) * ndof);
+    for (int64_t e = 0; e < nelem; ++e)
+        for (int I = 0; I < nd; ++I) yp[elem_dofs[e * nd + I]] += ypE[e * nd + I];
+    free(ypE);
+    free(U.L);
+    tables_free(&T);
+    return 0;
+}
+
+/* Row-sum lumped masses: mu[e][J] = sum_q w detJ rho psi_J (the same for each velocity
+   component), mp[i] = sum_e sum_q w detJ phi_I / bulk (assembled). */
+int orc_mixed_lumped(int64_t nelem, const double *vert, const int32_t *hex, const int32_t *elem_dofs, int p, int pu,
+                     int q, double rho, double bulk, int64_t ndof, double *mu, double *mp)
+{
+    tables T;
+    utables U;
+    if (tables_init(&T, p, q)) return -1;
+    if (utables_init(&U, pu, q, T.qx)) { tables_free(&T); return -1; }
+    const int nd = T.nd, nu = U.nu, du = U.du;
+    double *mpE = (double *)malloc(sizeof(double) * nelem * nd);
+#pragma omp parallel
+    {
+        double *phi = (double *)malloc(sizeof(double) * nd);
+        double *gphi = (double *)malloc(sizeof(double) * 3 * nd);
+#pragma omp for
+        for (int64_t e = 0; e < nelem; ++e) {
+            double X[24];
+            gather_corners(vert, hex, e, X);
+            for (int J = 0; J < nu; ++J) mu[e * nu + J] = 0.0;
+            for (int I = 0; I < nd; ++I) mpE[e * nd + I] = 0.0;
+            for (int c = 0; c < q; ++c)
+                for (int b = 0; b < q; ++b)
+                    for (int a = 0; a < q; ++a) {
+                        double x[3];
+                        double wdet = basis_at_qp(&T, X, a, b, c, phi, gphi, x, NULL);
+                        for (int j3 = 0; j3 < du; ++j3)
+                            for (int j2 = 0; j2 < du; ++j2)
+                                for (int j1 = 0; j1 < du; ++j1)
+                                    mu[e * nu + j1 + du * (j2 + du * j3)] +=
+                                        wdet * rho * U.L[a * du + j1] * U.L[b * du + j2] * U.L[c * du + j3];
+                        for (int I = 0; I < nd; ++I) mpE[e * nd + I] += wdet * phi[I] / bulk;
+                    }
+        }
+        free(phi); free(gphi);
+    }
+    memset(mp, 0, sizeof(double) * ndof);
+    for (int64_t e = 0; e < nelem; ++e)
+        for (int I = 0; I < nd; ++I) mp[elem_dofs[e * nd + I]] += mpE[e * nd + I];
+    free(mpE);
+    free(U.L);
     tables_free(&T);
     return 0;
 }

@@ -95,3 +95,18 @@ def iterative_refinement(A64, b, inner_solve, rtol=1e-8, max_outer=100):
             break
         x = x + inner_solve(r)
     return x, len(hist) - 1, hist
+
+
+def rk4(f, u, p, dt, nsteps):
+    """Classical fourth-order Runge-Kutta for the pair (u, p) with (u', p') = f(u, p):
+    k1 = f(x), k2 = f(x + dt/2 k1), k3 = f(x + dt/2 k2), k4 = f(x + dt k3),
+    x <- x + dt/6 (k1 + 2 k2 + 2 k3 + k4)."""
+    u, p = np.array(u, dtype=np.float64), np.array(p, dtype=np.float64)
+    for _ in range(int(nsteps)):
+        k1u, k1p = f(u, p)
+        k2u, k2p = f(u + 0.5 * dt * k1u, p + 0.5 * dt * k1p)
+        k3u, k3p = f(u + 0.5 * dt * k2u, p + 0.5 * dt * k2p)
+        k4u, k4p = f(u + dt * k3u, p + dt * k3p)
+        u = u + dt / 6.0 * (k1u + 2.0 * k2u + 2.0 * k3u + k4u)
+        p = p + dt / 6.0 * (k1p + 2.0 * k2p + 2.0 * k3p + k4p)
+    return u, p
