@@ -359,6 +359,53 @@ int pa_lp_save(pa_lp *lp, const char *path);
 int pa_lp_load(pa_lp *lp, const char *path);
 void pa_lp_destroy(pa_lp *lp);
 
+/* ------------------------------------------------------------------ the paper's operator
+   The off-diagonal blocks of the acoustic-gravity block operator (Sec. II-C, eq. (4)):
+   pressure p in the continuous order-p space (GLL nodes; DOF map and numbering as for
+   pa_setup on a structured box), velocity u in the discontinuous order-pu space (Lagrange
+   basis on the pu+1 Gauss-Legendre points per axis, three scalar components, stored
+   element by element: u[e][c][J], J = j1 + du (j2 + du j3), du = pu + 1), q1d-point Gauss
+   rule.  With the quadrature-point data E_cm = w adj(J)_mc (9 values per point, stored
+   FP64 [nelem][9][q1d^3]):
+       G p   = (grad p, tau)  (velocity space),
+       G^T u = (u, grad v)    (pressure space).
+   Supported (p, pu, q1d): (4, 3, 5), the paper's discretisation, and (2, 1, 3). */
+typedef struct pa_mixed pa_mixed;
+typedef struct {
+    int32_t p, pu, q1d;
+    int32_t pad_;
+    double rho;  /* density: velocity mass (rho u, tau) */
+    double bulk; /* bulk modulus K: pressure mass (K^{-1} p, v) */
+} pa_mixed_desc;
+typedef struct {
+    int32_t p, pu, q1d, nelem;
+    int32_t ndof_p;          /* pressure DOFs ((n p + 1)^3 on an n^3 box) */
+    int32_t ndof_u;          /* velocity DOFs, nelem * 3 * (pu+1)^3 */
+    int32_t elems_per_block; /* elements per workgroup of the fused kernel */
+    int32_t pad_;
+    int64_t qdata_bytes;
+} pa_mixed_info_t;
+/* Build the operator on a structured box (mesh->nx = ny = nz > 0; elem_dofs and ess_mode
+   are ignored): DOF map, 1-D tables of both spaces and E_cm on the device.  PA_ERR_MESH if
+   det J <= 0 at a quadrature point.  Synchronous. */
+int pa_mixed_setup(const pa_mesh_desc *mesh, const pa_mixed_desc *desc, void *stream, pa_mixed **out);
+/* yu = G p and yp = -G^T u in one fused kernel (Sec. III-G: D and D^T applied in the same
+   kernel; the pressure scatter by atomics): device vectors u, yu [ndof_u], p, yp [ndof_p];
+   outputs overwritten and not aliasing inputs.  Asynchronous. */
+int pa_mixed_apply(pa_mixed *m, const double *u, const double *p, double *yu, double *yp, void *stream);
+/* Row-sum lumped masses: mu [nelem][(pu+1)^3] = rho sum_q w detJ psi_J (the same for each
+   velocity component), mp [ndof_p] = sum_e sum_q w detJ phi_I / bulk.  Asynchronous. */
+int pa_mixed_lumped(pa_mixed *m, double *mu, double *mp, void *stream);
+/* nsteps classical RK4 steps of the semi-discrete system with lumped masses (Sec. II-C,
+   no boundary terms: u . n = 0 on the box): u' = -Mu^{-1} G p, p' = Mp^{-1} G^T u.  u and p
+   (device) are advanced in place; four fused applies per step; handle-owned work vectors
+   (allocated on first use).  Asynchronous. */
+int pa_mixed_rk4(pa_mixed *m, double *u, double *p, double dt, int nsteps, void *stream);
+/* As pa_set_grid_cap, for the fused mixed kernel (tests of the multi-group walk). */
+int pa_mixed_set_grid_cap(pa_mixed *m, int max_workgroups);
+int pa_mixed_info(const pa_mixed *m, pa_mixed_info_t *info);
+void pa_mixed_destroy(pa_mixed *m);
+
 /* ------------------------------------------------------------------ diagnostics */
 
 /* One FP64 MFMA on the device, writing the raw accumulator so a test can pin which entry

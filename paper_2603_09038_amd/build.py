@@ -26,9 +26,9 @@ def _units():
     units = []
     for p in range(1, 9):
         units.append(("k_apply.hip", f"k_apply_p{p}.o", [f"-DHEXPA_APPLY_P={p}"]))
-    for src in ("k_setup.hip", "k_diag.hip", "k_vec.hip", "k_debug.hip", "k_nn.hip", "noalloc.hip"):
+    for src in ("k_setup.hip", "k_diag.hip", "k_vec.hip", "k_debug.hip", "k_nn.hip", "noalloc.hip", "k_mixed.hip"):
         units.append((src, src.replace(".hip", ".o"), []))
-    for src in ("api.cpp", "tables.cpp", "learned.cpp"):
+    for src in ("api.cpp", "tables.cpp", "learned.cpp", "mixed.cpp"):
         units.append((src, src.replace(".cpp", ".o"), ["-x", "hip"]))
     return units
 

@@ -24,6 +24,9 @@ struct Tables1D {
     std::vector<double> B, G;               // [q][d]: l_i(x_a), l_i'(x_a)
 };
 bool make_tables(int p, int q, Tables1D &t, std::string &err);
+// Discontinuous (L2) space of order pu: Lagrange basis on the pu+1 Gauss-Legendre points,
+// values (and derivatives) at the q Gauss points
+bool make_l2_tables(int pu, int q, Tables1D &t, std::string &err);
 
 // Device-side 1-D table block: B[q][d], G[q][d] packed (kMaxQ*kMaxD each).
 struct DevTables {

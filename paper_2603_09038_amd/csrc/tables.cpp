@@ -120,4 +120,20 @@ bool make_tables(int p, int q, Tables1D &t, std::string &err)
     return true;
 }
 
+bool make_l2_tables(int pu, int q, Tables1D &t, std::string &err)
+{
+    if (pu < 0 || pu + 1 > kMaxD || q < 1 || q > kMaxQ) {
+        err = "velocity order/quadrature out of range";
+        return false;
+    }
+    t.p = pu; t.d = pu + 1; t.q = q;
+    std::vector<double> w;
+    gauss_legendre(t.d, t.nodes, w);  // velocity nodes: the pu+1 Gauss-Legendre points
+    gauss_legendre(q, t.qpts, t.qwts);
+    t.B.assign((size_t)q * t.d, 0.0);
+    t.G.assign((size_t)q * t.d, 0.0);
+    for (int a = 0; a < q; ++a) lagrange_bary(t.nodes, t.qpts[a], &t.B[(size_t)a * t.d], &t.G[(size_t)a * t.d]);
+    return true;
+}
+
 }  // namespace hexpa

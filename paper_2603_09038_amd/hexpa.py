@@ -32,7 +32,9 @@ EXPORTS = ("pa_setup", "pa_apply", "pa_apply_add", "pa_apply_lp", "pa_apply_unfu
            "cg_solve", "pa_debug_mfma_f64", "pa_debug_mfma16",
            "pa_lp_create", "pa_lp_bind", "pa_lp_configure", "pa_lp_num_params", "pa_lp_get_params",
            "pa_lp_set_params", "pa_lp_logk", "pa_lp_apply", "pa_lp_coarse", "pa_lp_net", "pa_lp_loss_grad",
-           "pa_lp_train_step", "pa_lp_train", "pa_lp_save", "pa_lp_load", "pa_lp_destroy")
+           "pa_lp_train_step", "pa_lp_train", "pa_lp_save", "pa_lp_load", "pa_lp_destroy",
+           "pa_mixed_setup", "pa_mixed_apply", "pa_mixed_lumped", "pa_mixed_rk4", "pa_mixed_set_grid_cap",
+           "pa_mixed_info", "pa_mixed_destroy")
 
 
 class HexpaError(RuntimeError):
@@ -91,6 +93,16 @@ class TrainLog(ctypes.Structure):
                 ("seconds_capture", ctypes.c_double), ("seconds_train", ctypes.c_double)]
 
 
+class MixedDesc(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("pu", ctypes.c_int32), ("q1d", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("bulk", ctypes.c_double)]
+
+
+class MixedInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("p", "pu", "q1d", "nelem", "ndof_p", "ndof_u", "elems_per_block",
+                                              "pad_")] + [("qdata_bytes", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
@@ -130,6 +142,12 @@ def _load():
         "pa_lp_loss_grad": [vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp],
         "pa_lp_train_step": [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp],
         "pa_lp_train": [vp, ctypes.POINTER(TrainSet), ctypes.POINTER(TrainLog), vp],
+        "pa_mixed_setup": [ctypes.POINTER(MeshDesc), ctypes.POINTER(MixedDesc), vp, ctypes.POINTER(vp)],
+        "pa_mixed_apply": [vp, vp, vp, vp, vp, vp],
+        "pa_mixed_lumped": [vp, vp, vp, vp],
+        "pa_mixed_rk4": [vp, vp, vp, ctypes.c_double, i32, vp],
+        "pa_mixed_set_grid_cap": [vp, i32],
+        "pa_mixed_info": [vp, ctypes.POINTER(MixedInfo)],
         "pa_lp_save": [vp, ctypes.c_char_p],
         "pa_lp_load": [vp, ctypes.c_char_p],
     }
@@ -141,6 +159,8 @@ def _load():
     lib.pa_destroy.restype = None
     lib.pa_lp_destroy.argtypes = [vp]
     lib.pa_lp_destroy.restype = None
+    lib.pa_mixed_destroy.argtypes = [vp]
+    lib.pa_mixed_destroy.restype = None
     lib.pa_last_error.argtypes = []
     lib.pa_last_error.restype = ctypes.c_char_p
     return lib
@@ -553,6 +573,63 @@ class LearnedPreconditioner:
     def close(self):
         if self.h:
             pa_lp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MixedOperator:
+    """Owns a pa_mixed handle: the off-diagonal blocks of the acoustic operator (thin
+    convenience over the pa_mixed_* calls)."""
+
+    def __init__(self, mesh, p=4, pu=3, q1d=5, rho=1.0, bulk=1.0, stream=None):
+        vert = np.ascontiguousarray(mesh["vert"], dtype=np.float64)
+        hexes = np.ascontiguousarray(mesh["hex"], dtype=np.int32)
+        md = MeshDesc()
+        md.nvert, md.vert_xyz = vert.shape[0], vert.ctypes.data
+        md.nelem, md.hex = hexes.shape[0], hexes.ctypes.data
+        md.nx = md.ny = md.nz = int(mesh["n"])
+        desc = MixedDesc(int(p), int(pu), int(q1d), 0, float(rho), float(bulk))
+        h = ctypes.c_void_p()
+        _check(_lib.pa_mixed_setup(ctypes.byref(md), ctypes.byref(desc), _stream(stream), ctypes.byref(h)))
+        self.h = h
+        info = MixedInfo()
+        _check(_lib.pa_mixed_info(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in MixedInfo._fields_ if f != "pad_"}
+        self.ndof_p, self.ndof_u, self.nelem = info.ndof_p, info.ndof_u, info.nelem
+        self.nu = (int(pu) + 1) ** 3
+
+    def _vec(self, n):
+        import torch
+        return torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def apply(self, u, p, yu=None, yp=None, stream=None):
+        yu = self._vec(self.ndof_u) if yu is None else yu
+        yp = self._vec(self.ndof_p) if yp is None else yp
+        _check(_lib.pa_mixed_apply(self.h, _dptr(u, n=self.ndof_u), _dptr(p, n=self.ndof_p),
+                                   _dptr(yu, n=self.ndof_u), _dptr(yp, n=self.ndof_p), _stream(stream)))
+        return yu, yp
+
+    def lumped(self, stream=None):
+        mu = self._vec(self.nelem * self.nu)
+        mp = self._vec(self.ndof_p)
+        _check(_lib.pa_mixed_lumped(self.h, _dptr(mu), _dptr(mp), _stream(stream)))
+        return mu, mp
+
+    def rk4(self, u, p, dt, nsteps, stream=None):
+        _check(_lib.pa_mixed_rk4(self.h, _dptr(u, n=self.ndof_u), _dptr(p, n=self.ndof_p), float(dt), int(nsteps),
+                                 _stream(stream)))
+
+    def set_grid_cap(self, n):
+        _check(_lib.pa_mixed_set_grid_cap(self.h, int(n)))
+
+    def close(self):
+        if self.h:
+            _lib.pa_mixed_destroy(self.h)
             self.h = None
 
     def __del__(self):
