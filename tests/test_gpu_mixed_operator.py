@@ -34,7 +34,7 @@ def _rel(a, b):
     return max(np.linalg.norm(a - b) / np.linalg.norm(b), np.abs(a - b).max() / np.abs(b).max())
 
 
-@pytest.mark.parametrize("p,pu,q,n", [(4, 3, 5, 3), (2, 1, 3, 4)])
+@pytest.mark.parametrize("p,pu,q,n", [(4, 3, 5, 3), (2, 1, 3, 8)])
 def test_fused_apply_matches_the_oracle(hx, p, pu, q, n):
     """yu = G p and yp = -G^T u against the dense element matrices, with the persistent
     grid uncapped (one group per workgroup) and capped (8 and 3 workgroups: each walks
