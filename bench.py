@@ -10,7 +10,9 @@ Headline (one step = one fused FP64 diffusion apply y = K x at each of p = 2, 4,
   with HIP events on its launch stream inside the timed region (per-order GDOF/s and
   fraction of the 8 TB/s HBM roof), and the mass operator at the same sizes afterwards.
 
-Further legs (each can be switched off): the 48^3 p=4 sine-coefficient operator (kernel
+Further legs (each can be switched off): the paper's own operator (the fused kernel of the
+off-diagonal blocks of the acoustic operator, H1 p=4 x L2 p=3, Q1D=5, and its RK4 step);
+the 48^3 p=4 sine-coefficient operator (kernel
 roofline, the unfused / fused / matrix-free x vector-ALU / MFMA kernel matrix, MDOF/W,
 Jacobi-PCG to 1e-8 with its per-iteration roofline fraction); mixed precision on the
 32^3 p=6 log-normal workload; the learned preconditioner on the 32^3 p=4 log-normal
@@ -546,6 +548,50 @@ def run_learned(hexpa, ntrain, nheld, n=32, p=4, weights=None):
     return out
 
 
+def run_paper_operator(hexpa, n=48, steps=50):
+    """The paper's own operator (the off-diagonal blocks of the acoustic operator, eq. (4)):
+    pressure H1 p=4, velocity L2 p=3 (three components), Q1D=5, on the 48^3 perturbed mesh
+    (7,189,057 pressure + 21,233,664 velocity DOFs): the fused kernel applying D and D^T in
+    one pass, timed by HIP events, and one lumped-mass RK4 step (four applies)."""
+    import torch
+    import synth
+    mesh = synth.box_mesh(n, perturb=0.1, seed=0)
+    m = hexpa.MixedOperator(mesh)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    u = torch.rand(m.ndof_u, dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+    p = torch.rand(m.ndof_p, dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+    yu, yp = torch.empty_like(u), torch.empty_like(p)
+    warm(lambda: m.apply(u, p, yu, yp), 0.3, 3)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        m.apply(u, p, yu, yp)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nd = m.ndof_u + m.ndof_p
+    # D (9 FP64 per point), the pressure map, read u and p, write yu and yp
+    alg = m.nelem * 9 * 125 * 8 + m.nelem * 125 * 4 + 16 * (m.ndof_u + m.ndof_p)
+    out = {"workload": f"{n}^3 perturbed hex mesh, pressure H1 p=4 (GLL), velocity L2 p=3 (Gauss-Legendre nodes, "
+                       f"3 components), Q1D=5, rho=K=1", "ndof_pressure": m.ndof_p, "ndof_velocity": m.ndof_u,
+           "elems_per_group": m.info["elems_per_block"], "apply_ms_with_fill": ms, "gdofs": nd / ms / 1e6,
+           "alg_bytes": alg, "hbm_frac": alg / ms / 1e6 / HBM_PEAK_GBS,
+           "paper_context": "GB200 DMMA Fused PA 46.60 GDOF/s, GH200 36.15 GDOF/s at 540 M DOFs (Table VI)"}
+    m.rk4(u * 1e-3, p * 1e-3, 1e-4, 2)
+    torch.cuda.synchronize()
+    e0.record(s)
+    m.rk4(u, p, 1e-5, 10)
+    e1.record(s)
+    torch.cuda.synchronize()
+    out["rk4_step_ms"] = e0.elapsed_time(e1) / 10
+    log(f"paper operator: fused apply {ms:.4f} ms = {out['gdofs']:.1f} GDOF/s ({100 * out['hbm_frac']:.1f} % of HBM roof), "
+        f"RK4 step {out['rk4_step_ms']:.3f} ms")
+    m.close()
+    return out
+
+
 def _oracle_assembled_apply(oracle, P, sub):
     """Element matrices of the listed elements (timed: assembly), then y = sum_e G_e^T A_e G_e x
     over them by the oracle's assembled apply, on a compact numbering of the DOFs they touch
@@ -653,6 +699,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-paper-operator", action="store_true", help="skip the mixed H1 x L2 acoustic operator")
     ap.add_argument("--no-matrix", action="store_true", help="skip the unfused/fused/matrix-free kernel matrix")
     ap.add_argument("--no-energy", action="store_true", help="skip the MDOF/W measurement")
     ap.add_argument("--learned-train", type=int, default=200, help="training draws of the learned preconditioner")
@@ -703,6 +750,8 @@ def main():
     }
     if not args.no_mass:
         out["sweep_mass"] = run_mass_sweep(hexpa, orders)
+    if not args.no_paper_operator:
+        out["paper_operator"] = run_paper_operator(hexpa)
     if not args.no_c2:
         out["c2"] = run_c2(hexpa, args)
     if not args.no_mixed:
