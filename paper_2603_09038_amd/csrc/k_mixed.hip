@@ -74,7 +74,7 @@ struct MixShape {
 };
 
 template <int DP, int DU, int Q>
-__global__ __launch_bounds__(256, 2) void k_mixed(int nelem, int ngroups, const int32_t *__restrict__ emap,
+__global__ __launch_bounds__(256, 3) void k_mixed(int nelem, int ngroups, const int32_t *__restrict__ emap,
                                                   const double *__restrict__ qd, const DevTables *__restrict__ tabp,
                                                   const DevTables *__restrict__ tabu, const double *__restrict__ pv,
                                                   const double *__restrict__ u, double *__restrict__ yu,
@@ -92,11 +92,13 @@ __global__ __launch_bounds__(256, 2) void k_mixed(int nelem, int ngroups, const 
     __shared__ double bufVB[E * MS::SZ_VB];
     __shared__ int32_t lmap[E * D3];
     const int tid = threadIdx.x;
-    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
-        const int e0 = g * E, nv = min(E, nelem - e0);
-        // D of the group into registers (9 values per quadrature point), used after the
-        // forward passes
-        double dq[NS][9];
+    // Persistent workgroups walking a strided list of element groups.  While group g is
+    // contracted, the next group's DOF map, pressure gather and velocity are loaded into
+    // registers (after the forward passes), and its D after the D-step.
+    constexpr int NMP = (E * D3 + NT - 1) / NT;      // map / pressure slots per thread
+    constexpr int NMU = (E * 3 * NU + NT - 1) / NT;  // velocity slots per thread
+    auto load_d = [&](int gg, double (&dq)[NS][9]) {
+        const int e0 = gg * E, nv = min(E, nelem - e0);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int L = tid + s * NT;
@@ -106,17 +108,62 @@ __global__ __launch_bounds__(256, 2) void k_mixed(int nelem, int ngroups, const 
 #pragma unroll
             for (int c = 0; c < 9; ++c) dq[s][c] = ok ? __builtin_nontemporal_load(src + c * Q3) : 0.0;
         }
-        // gather p and the DOF map; load the element-local velocity
-        for (int L = tid; L < E * D3; L += NT) {
+    };
+    auto load_map = [&](int gg, int32_t (&mm)[NMP]) {
+        const int e0 = gg * E, nv = gg < ngroups ? min(E, nelem - e0) : 0;
+#pragma unroll
+        for (int s = 0; s < NMP; ++s) {
+            const int L = tid + s * NT;
             const int e = L / D3, I = L - e * D3;
-            const int m = e < nv ? emap[(int64_t)(e0 + e) * D3 + I] : -1;
-            lmap[L] = m;
-            bufA[e * MS::SZ_A + I] = m >= 0 ? pv[m] : 0.0;  // no padding at these orders: X[n][i] is natural
+            mm[s] = (L < E * D3 && e < nv) ? emap[(int64_t)(e0 + e) * D3 + I] : -1;
         }
-        for (int L = tid; L < E * 3 * NU; L += NT) {
-            const int e = L / (3 * NU), r = L - e * 3 * NU;
-            bufVA[e * MS::SZ_VA + r] = e < nv ? u[(int64_t)(e0 + e) * 3 * NU + r] : 0.0;
+    };
+    auto load_p = [&](const int32_t (&mm)[NMP], double (&pp)[NMP]) {
+#pragma unroll
+        for (int s = 0; s < NMP; ++s) pp[s] = mm[s] >= 0 ? pv[mm[s]] : 0.0;
+    };
+    auto load_u = [&](int gg, double (&uu)[NMU]) {
+        const int e0 = gg * E, nv = gg < ngroups ? min(E, nelem - e0) : 0;
+#pragma unroll
+        for (int s = 0; s < NMU; ++s) {
+            const int L = tid + s * NT;
+            const int e = L / (3 * NU);
+            uu[s] = (L < E * 3 * NU && e < nv) ? u[(int64_t)e0 * 3 * NU + L] : 0.0;
         }
+    };
+    int g = blockIdx.x;
+    if (g >= ngroups) return;
+    double dq[NS][9], pcur[NMP], ucur[NMU];
+    int32_t mcur[NMP];
+    load_d(g, dq);
+    load_map(g, mcur);
+    load_p(mcur, pcur);
+    load_u(g, ucur);
+    for (;;) {
+        const int e0 = g * E, nv = min(E, nelem - e0);
+        const int gn = g + gridDim.x;
+        const bool more = gn < ngroups;
+        // stage the group: the DOF map, the pressure tile (unpadded at these orders, so
+        // X[n][i] is the natural node order) and the element-local velocity
+#pragma unroll
+        for (int s = 0; s < NMP; ++s) {
+            const int L = tid + s * NT;
+            if (L < E * D3) {
+                const int e = L / D3, I = L - e * D3;
+                lmap[L] = mcur[s];
+                bufA[e * MS::SZ_A + I] = pcur[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NMU; ++s) {
+            const int L = tid + s * NT;
+            if (L < E * 3 * NU) {
+                const int e = L / (3 * NU), r = L - e * 3 * NU;
+                bufVA[e * MS::SZ_VA + r] = ucur[s];
+            }
+        }
+        int32_t mnext[NMP];
+        load_map(gn, mnext);
         mx_barrier();
 
         // forward passes: the pressure gradient (B and G along each axis) and the velocity
@@ -138,6 +185,9 @@ __global__ __launch_bounds__(256, 2) void k_mixed(int nelem, int ngroups, const 
         valu_pass<VFwd<DU, Q, 0, 2>, E, NT>(bufVA, MS::SZ_VA, tabu, LdsOut<double>{bufVB, MS::SZ_VB}, tid);
         valu_pass<VFwd<DU, Q, 1, 2>, E, NT>(bufVA, MS::SZ_VA, tabu, LdsOut<double>{bufVB, MS::SZ_VB}, tid);
         valu_pass<VFwd<DU, Q, 2, 2>, E, NT>(bufVA, MS::SZ_VA, tabu, LdsOut<double>{bufVB, MS::SZ_VB}, tid);
+        double pnext[NMP], unext[NMU];
+        load_p(mnext, pnext);  // the next group's map has had the forward passes to arrive
+        load_u(gn, unext);
         mx_barrier();
 
         // D and D^T at the quadrature points: v = E grad_ref p into the velocity channels,
@@ -160,6 +210,7 @@ __global__ __launch_bounds__(256, 2) void k_mixed(int nelem, int ngroups, const 
                 G[CH::Z] = -(Em[2] * u0 + Em[5] * u1 + Em[8] * u2);
             }
         }
+        if (more) load_d(gn, dq);  // the next group's D, in flight during the transposed passes
         mx_barrier();
 
         // transposed passes: the gradient-transpose of w into the pressure space (scatter-add),
@@ -182,7 +233,16 @@ __global__ __launch_bounds__(256, 2) void k_mixed(int nelem, int ngroups, const 
         valu_pass<VTrn<DU, Q, 0, 2>, E, NT>(bufVB, MS::SZ_VB, tabu, dout, tid);
         valu_pass<VTrn<DU, Q, 1, 2>, E, NT>(bufVB, MS::SZ_VB, tabu, dout, tid);
         valu_pass<VTrn<DU, Q, 2, 2>, E, NT>(bufVB, MS::SZ_VB, tabu, dout, tid);
+        if (!more) break;
         mx_barrier();  // LDS is rewritten by the next group
+        g = gn;
+#pragma unroll
+        for (int s = 0; s < NMP; ++s) {
+            mcur[s] = mnext[s];
+            pcur[s] = pnext[s];
+        }
+#pragma unroll
+        for (int s = 0; s < NMU; ++s) ucur[s] = unext[s];
     }
 }
 
