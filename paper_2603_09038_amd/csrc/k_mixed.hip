@@ -58,7 +58,7 @@ struct DirectOut {
     }
 };
 
-template <int DP, int DU, int Q>
+template <int DP, int DU, int Q, int NT_ = 128, int BUDGET = kMixLdsBudget / 2>
 struct MixShape {
     using S = Shape<DP, Q, 2>;  // the pressure chain: the diffusion kernel's tensors
     static constexpr int NU = DU * DU * DU, Q3 = Q * Q * Q, D3 = DP * DP * DP;
@@ -68,13 +68,13 @@ struct MixShape {
     static constexpr int SZ_VA = cmax(3 * NU, 3 * Q * Q * DU) | 1;
     static constexpr int SZ_VB = cmax(3 * Q * DU * DU, 3 * Q3) | 1;
     static constexpr int PER = 8 * (SZ_A + SZ_B + SZ_VA + SZ_VB) + 4 * D3;
-    static constexpr int E = cclamp(kMixLdsBudget / PER, 1, 16);
-    static constexpr int NT = 256;
+    static constexpr int E = cclamp(BUDGET / PER, 1, 16);
+    static constexpr int NT = NT_;
     static constexpr int NS = (E * Q3 + NT - 1) / NT;  // quadrature-point slots per thread
 };
 
 template <int DP, int DU, int Q>
-__global__ __launch_bounds__(256, 3) void k_mixed(int nelem, int ngroups, const int32_t *__restrict__ emap,
+__global__ __launch_bounds__(128, 3) void k_mixed(int nelem, int ngroups, const int32_t *__restrict__ emap,
                                                   const double *__restrict__ qd, const DevTables *__restrict__ tabp,
                                                   const DevTables *__restrict__ tabu, const double *__restrict__ pv,
                                                   const double *__restrict__ u, double *__restrict__ yu,
