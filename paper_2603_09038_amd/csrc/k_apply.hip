@@ -485,17 +485,20 @@ struct DmaShape {
     static constexpr int FIXED = TB * 2 * SLACK + (int)sizeof(DevTables);
     static constexpr int E = cclamp((kDmaLdsBudget - FIXED) / PER, 1, 32);
     static constexpr bool ok = D >= kDmaMinD;
+    // one element per group at p = 8: eight waves share it (each pass has 6-7 column tiles)
+    static constexpr int NT = (E == 1 && D >= 9) ? 512 : kThreads;
 };
 
 template <int D, int Q, int OPS, int EX, bool ATOMIC>
-__global__ __launch_bounds__(kThreads, kMinWavesPerEU) void k_apply_dma(
+__global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
+                             (DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT == 512 ? 2 : kMinWavesPerEU)) void k_apply_dma(
     int nelem, int ngroups, const int32_t *__restrict__ elist, const int32_t *__restrict__ emap,
     const typename ExT<EX>::T *__restrict__ qd, const DevTables *__restrict__ tab,
     const typename ExT<EX>::T *__restrict__ x, typename ExT<EX>::T *__restrict__ y)
 {
     using T = typename ExT<EX>::T;
     using S = Shape<D, Q, OPS, (int)sizeof(T)>;
-    constexpr int NT = kThreads;
+    constexpr int NT = DmaShape<D, Q, OPS, T>::NT;
     constexpr int E = DmaShape<D, Q, OPS, T>::E, D3 = S::D3, Q3 = S::Q3, NC = S::NCOMP, ED3 = E * D3;
     constexpr int NSD = (E * Q3 + NT - 1) / NT;
     constexpr bool M = S::kMass, WIDE = sizeof(T) == 8;
@@ -749,7 +752,7 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
     constexpr bool DMA = DmaShape<D, Q, OPS, T>::ok;
     // elements per group and workgroup size exactly as the chosen kernel computes them
     constexpr int EG = DMA ? DmaShape<D, Q, OPS, T>::E : Shape<D, Q, OPS, (int)sizeof(T), CFG::NT, CFG::BUDGET>::E;
-    constexpr int NT = DMA ? kThreads : CFG::NT;
+    constexpr int NT = DMA ? DmaShape<D, Q, OPS, T>::NT : CFG::NT;
     const int ngroups = (n + EG - 1) / EG;
     if (ngroups == 0) return hipSuccess;
     if constexpr (!DMA) {
@@ -841,7 +844,7 @@ static void group_shape(int *elems, int *threads)
     using CFG = ApplyCfg<D, OPS, EX>;
     constexpr bool DMA = FUSED_STORED && DmaShape<D, Q, OPS, T>::ok;
     *elems = DMA ? DmaShape<D, Q, OPS, T>::E : Shape<D, Q, OPS, (int)sizeof(T), CFG::NT, CFG::BUDGET>::E;
-    *threads = DMA ? kThreads : CFG::NT;
+    *threads = DMA ? DmaShape<D, Q, OPS, T>::NT : CFG::NT;
 }
 
 template <int D, int Q, int OPS>
