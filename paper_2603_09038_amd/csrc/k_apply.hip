@@ -42,50 +42,6 @@ __device__ __forceinline__ int xpos(int I)
 {
     return I + (S::DP - S::ND) * (I / S::ND);
 }
-// Scatter-add of a group's element outputs y_E (staged in LDS, natural node order per
-// element at stride SZ) through the DOF map.  Consecutive elements of a group are usually
-// neighbours along x (elements are ordered x fastest): the right face (i = D-1) of element
-// e and the left face (i = 0) of element e+1 then hold the same DOFs, and their two
-// contributions are summed here so that each such DOF gets one global addition instead of
-// two.  Whether the faces coincide is read from the map itself (equal DOF numbers), so
-// any element order and mesh stay exact; only the merging opportunity depends on it.
-// Lanes walk the group in row order (node row (j,k), then element, then i), so a wave's
-// atomics cover runs of consecutive DOFs across the group's elements instead of D-long
-// pieces of many rows: FP64 atomics are executed beyond the L2 per cache line requested,
-// and this order cuts the lines per instruction several-fold (measured: the mass apply
-// 1.2-1.45x faster at p = 2..6).
-template <int D, int E, int NT, int SZ, bool ATOMIC, class T>
-__device__ __forceinline__ void scatter_group(const T *stage, const int32_t *lmap, T *y, int tid)
-{
-    constexpr int D3 = D * D * D, ROW = E * D;
-    for (int R = tid; R < E * D3; R += NT) {
-        const int jk = R / ROW, t = R - jk * ROW;
-        const int e = t / D, i = t - e * D;
-        const int I = i + D * jk, L = e * D3 + I;
-        const int32_t g = lmap[L];
-        if (g < 0) continue;
-        if (i == 0 && e > 0 && lmap[L - D3 + (D - 1)] == g) continue;  // added by the left neighbour
-        T v = stage[e * SZ + I];
-        if (i == D - 1 && e + 1 < E && lmap[L + D3 - (D - 1)] == g) v += stage[(e + 1) * SZ + I - (D - 1)];
-        if (ATOMIC)
-            unsafeAtomicAdd(y + g, v);
-        else
-            y[g] += v;
-    }
-}
-
-// Row order of a group's nodes (row (j,k), then element, then i): slot R -> element e and
-// local node I = i + D (j + D k).  The register kernel gathers x in this order, so the
-// lanes of one load read consecutive DOFs of a row across the group's elements.
-template <int D, int E>
-__device__ __forceinline__ void row_node(int R, int &e, int &I)
-{
-    constexpr int ROW = E * D;
-    const int jk = R / ROW, t = R - jk * ROW;
-    e = t / D;
-    I = t - e * D + D * jk;
-}
-
 // Centre every staged x tile on its element mean (the BF16 diffusion apply).  Diffusion
 // annihilates constants element by element (the reference gradients of the basis sum to
 // zero), so y_E is unchanged in exact arithmetic, while the 16-bit rounding of the tile at

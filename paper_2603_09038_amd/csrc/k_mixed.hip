@@ -114,7 +114,8 @@ __global__ __launch_bounds__(128, 3) void k_mixed(int nelem, int ngroups, const 
 #pragma unroll
         for (int s = 0; s < NMP; ++s) {
             const int L = tid + s * NT;
-            const int e = L / D3, I = L - e * D3;
+            int e, I;
+            row_node<DP, E>(L, e, I);
             mm[s] = (L < E * D3 && e < nv) ? emap[(int64_t)(e0 + e) * D3 + I] : -1;
         }
     };
@@ -149,8 +150,9 @@ __global__ __launch_bounds__(128, 3) void k_mixed(int nelem, int ngroups, const 
         for (int s = 0; s < NMP; ++s) {
             const int L = tid + s * NT;
             if (L < E * D3) {
-                const int e = L / D3, I = L - e * D3;
-                lmap[L] = mcur[s];
+                int e, I;
+                row_node<DP, E>(L, e, I);
+                lmap[e * D3 + I] = mcur[s];
                 bufA[e * MS::SZ_A + I] = pcur[s];
             }
         }
@@ -228,11 +230,13 @@ __global__ __launch_bounds__(128, 3) void k_mixed(int nelem, int ngroups, const 
         valu_pass<VTrn<DU, Q, 1, 1>, E, NT>(bufVA, MS::SZ_VA, tabu, LdsOut<double>{bufVB, MS::SZ_VB}, tid);
         valu_pass<VTrn<DU, Q, 2, 1>, E, NT>(bufVA, MS::SZ_VA, tabu, LdsOut<double>{bufVB, MS::SZ_VB}, tid);
         mx_barrier();
-        valu_pass<DT3<DP, Q, false>, E, NT>(bufB, MS::SZ_B, tabp, GlobalOut<true, double>{yp, lmap, D3}, tid);
+        valu_pass<DT3<DP, Q, false>, E, NT>(bufB, MS::SZ_B, tabp, LdsOut<double>{bufA, MS::SZ_A}, tid);
         const DirectOut dout{yu + (int64_t)e0 * 3 * NU, 3 * NU, nv};
         valu_pass<VTrn<DU, Q, 0, 2>, E, NT>(bufVB, MS::SZ_VB, tabu, dout, tid);
         valu_pass<VTrn<DU, Q, 1, 2>, E, NT>(bufVB, MS::SZ_VB, tabu, dout, tid);
         valu_pass<VTrn<DU, Q, 2, 2>, E, NT>(bufVB, MS::SZ_VB, tabu, dout, tid);
+        mx_barrier();
+        scatter_group<DP, E, NT, MS::SZ_A, true>(bufA, lmap, yp, tid);
         if (!more) break;
         mx_barrier();  // LDS is rewritten by the next group
         g = gn;
