@@ -183,6 +183,38 @@ def test_persistent_multigroup_full_vector(hx, p):
 
 
 @pytest.mark.parametrize("p", [2, 4, 6, 8])
+def test_unstructured_element_order_full_vector(hx, p):
+    """The same operator with its elements listed in a random order and in reverse order
+    (an unstructured mesh: explicit element-to-DOF map).  Consecutive elements of a group are
+    then rarely x-neighbours, or neighbours on the other side, so the scatter's shared-face
+    merge mostly finds nothing to merge and the row-order gather reads scattered DOFs.  Full
+    vectors against the oracle (given the same element order) at 1e-12, uncapped and with each
+    workgroup walking several groups."""
+    n, q = MULTI[p], p + 2
+    mesh = synth.box_mesh(n, perturb=0.1, seed=140 + p)
+    ed = oracle.box_elem_dofs(n, p)
+    ndof = int(ed.max()) + 1
+    perm = np.random.default_rng(140 + p).permutation(n ** 3)
+    x = synth.rand_x(ndof, 140 + p)
+    xd = _cuda(x)
+    for order in (perm, np.arange(n ** 3)[::-1]):
+        m2 = {"vert": mesh["vert"], "hex": np.ascontiguousarray(mesh["hex"][order])}
+        ed2 = np.ascontiguousarray(ed[order])
+        for ops in (1, 2):
+            ref = oracle.Problem(m2, p, q, ops=_ops_o(ops), elem_dofs=ed2).apply(x)
+            op = hx.PAOperator(m2, p, q, ops=ops, structured=False, elem_dofs=ed2, ndof=ndof)
+            assert op.ndof == ndof
+            for variant in (hx.PA_VARIANT_MFMA, hx.PA_VARIANT_VALU):
+                op.set_variant(variant)
+                for cap in (0, 3):
+                    op.set_grid_cap(cap)
+                    y = op.apply(xd).cpu().numpy()
+                    assert _rel(y, ref) <= TOL, (p, ops, variant, cap, _rel(y, ref))
+                    assert np.max(np.abs(y - ref)) <= TOL * np.max(np.abs(ref)), (p, ops, variant, cap)
+            op.close()
+
+
+@pytest.mark.parametrize("p", [2, 4, 6, 8])
 def test_persistent_multigroup_lp_apply(hx, p):
     """The 16-bit apply on the same multi-group walk: within 8u of the FP64 oracle, and
     equal (up to the FP32 atomic order) to the uncapped launch."""
