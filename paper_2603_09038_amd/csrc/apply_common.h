@@ -161,6 +161,57 @@ __device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassReg
         }
 }
 
+// The 1-D basis as MFMA A-operands in registers for a whole kernel (FP64 MFMA executor,
+// Q a multiple of 4).  Every pass matrix is then a set of 4x4 tiles of one of two blocks
+//   F = [B; G]      rows o < Q: B[o][k], o >= Q: G[o-Q][k]; k < D (forward passes),
+//   T = [B^T G^T]   rows o < D; k < Q: B[k][o], k >= Q: G[k-Q][o] (transposed passes),
+// at whole tiles (pass row tile rt is block tile amrt(rt), k chunk kc is amkc(kc)), so the
+// tables are read once per kernel instead of once per pass and wave: at p = 6 that removes
+// about 60 % of the kernel's LDS instructions.  Lane l holds A[4 rt + (l & 3)][4 kc + (l >> 4)]
+// as in load_a; the values, and so the results, are those of the per-pass loads.
+template <int D, int Q, bool ON>
+struct ABlocks {
+    static constexpr bool on = ON;
+    static constexpr int QT = Q / 4;
+    static constexpr int RTF = ON ? 2 * QT : 1, KCF = ON ? (D + 3) / 4 : 1;
+    static constexpr int RTT = ON ? (D + 3) / 4 : 1, KCT = ON ? 2 * QT : 1;
+    double f[RTF][KCF], t[RTT][KCT];
+    __device__ __forceinline__ void load(const DevTables *tab, int lane)
+    {
+        if constexpr (ON) {
+            static_assert(Q % 4 == 0, "block tiles must not straddle the B / G boundary");
+            const int r = lane & 3, c = lane >> 4;
+#pragma unroll
+            for (int rt = 0; rt < RTF; ++rt)
+#pragma unroll
+                for (int kc = 0; kc < KCF; ++kc) {
+                    const int o = 4 * rt + r, k = 4 * kc + c;
+                    f[rt][kc] = k < D ? (o < Q ? tB(tab, o, k, D) : tG(tab, o - Q, k, D)) : 0.0;
+                }
+#pragma unroll
+            for (int rt = 0; rt < RTT; ++rt)
+#pragma unroll
+                for (int kc = 0; kc < KCT; ++kc) {
+                    const int o = 4 * rt + r, k = 4 * kc + c;
+                    t[rt][kc] = o < D ? (k < Q ? tB(tab, k, o, D) : tG(tab, k - Q, o, D)) : 0.0;
+                }
+        }
+    }
+    // the A-operand tiles of pass P
+    template <class P>
+    __device__ __forceinline__ void view(double (&a)[PassRegs<P>::RT][PassRegs<P>::KC]) const
+    {
+#pragma unroll
+        for (int rt = 0; rt < PassRegs<P>::RT; ++rt)
+#pragma unroll
+            for (int kc = 0; kc < PassRegs<P>::KC; ++kc)
+                if constexpr (P::AM == 0)
+                    a[rt][kc] = f[P::amrt(rt)][P::amkc(kc)];
+                else
+                    a[rt][kc] = t[P::amrt(rt)][P::amkc(kc)];
+    }
+};
+
 // Store policy of a pass output (LDS; the last pass stages y_E there for scatter_group).
 // `addr` is element-local (OUT + opos(n) + NCOLO o; the last pass writes the natural
 // node order n + D^2 o).

@@ -12,7 +12,9 @@
 //              in_off(t) + n C + c),
 //   A(tab,o,k) the stacked pass matrix (k = t C + c),
 //   OUT        offset of the output inside the element's output region: Out[o][n] is
-//              stored at OUT + n + NCOL o.
+//              stored at OUT + n + NCOL o,
+//   AM, amrt, amkc  where the pass's MFMA A-operand tiles sit in the two basis blocks that
+//              ABlocks keeps in registers (used when Q is a multiple of 4).
 // Because each stage stores its output as [o][n], the next stage's contracted index is
 // the fastest one in memory (the cyclic index order of the paper's Sec. III-D), and a
 // block of rows of one pass (e.g. its G rows) is itself a contiguous tensor.
@@ -37,6 +39,9 @@ struct Chan {
 // Forward x: X[n=(j,k)][i] -> U1[o1][n]: rows o1 < Q are B_x X (BX), rows >= Q are G_x X (GX).
 template <int D, int Q, bool M>
 struct DF1 {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D);
     static constexpr int NCOL = D * D, C = D, CS = DP, NT = 1, O = 2 * Q, OUT = 0, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return 0; }
@@ -45,6 +50,9 @@ struct DF1 {
 // Forward y on BX: BX[n=(k,a)][j] -> rows o2 < Q: T_BB = B_y BX, rows >= Q: T_BG = G_y BX.
 template <int D, int Q, bool M>
 struct DF2a {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D);
     static constexpr int NCOL = Q * D, C = D, CS = DP, NT = 1, O = 2 * Q, OUT = 0, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return 0; }
@@ -53,6 +61,9 @@ struct DF2a {
 // Forward y on GX: T_GB = B_y GX.
 template <int D, int Q, bool M>
 struct DF2b {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D);
     static constexpr int NCOL = Q * D, C = D, CS = DP, NT = 1, O = Q, OUT = 2 * Q * Q * DP, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return Q * D * DP; }
@@ -61,6 +72,9 @@ struct DF2b {
 // Forward z on T_BB[n=(a,b)][k]: dz = G_z T_BB (and u = B_z T_BB, stacked first, with mass).
 template <int D, int Q, bool M>
 struct DF3a {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return M ? rt : rt + Q / 4; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
     static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = M ? 2 * Q : Q, OUT = M ? Chan<Q, M>::V : Chan<Q, M>::Z;
     static constexpr int OF = Q, OSTR = QP;
@@ -73,6 +87,9 @@ struct DF3a {
 // Forward z on T_BG: dy = B_z T_BG.
 template <int D, int Q, bool M>
 struct DF3b {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
     static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = Q, OUT = Chan<Q, M>::Y, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return Q * Q * DP; }
@@ -81,6 +98,9 @@ struct DF3b {
 // Forward z on T_GB: dx = B_z T_GB.
 template <int D, int Q, bool M>
 struct DF3c {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
     static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = Q, OUT = Chan<Q, M>::X, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 2 * Q * Q * DP; }
@@ -89,6 +109,9 @@ struct DF3c {
 // Transposed x of one channel: V_ch[n=(b,c)][a] -> W_slot[i][n] with G^T (dx) or B^T.
 template <int D, int Q, bool M, int CH_OFF, int SLOT, bool GT>
 struct DT1 {
+    static constexpr int AM = 1;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return GT ? kc + Q / 4 : kc; }
     static constexpr int QP = pad_stride(Q);
     static constexpr int NCOL = Q * Q, C = Q, CS = QP, NT = 1, O = D, OUT = SLOT * Q * QP * D, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return CH_OFF; }
@@ -98,6 +121,9 @@ struct DT1 {
 // Transposed y, path continuing with B_z^T: t1 = B_y^T W0 + G_y^T W1 (+ B_y^T W3).
 template <int D, int Q, bool M>
 struct DT2a {
+    static constexpr int AM = 1;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc % (Q / 4) + (kc / (Q / 4) == 1 ? Q / 4 : 0); }
     static constexpr int QP = pad_stride(Q);
     static constexpr int NCOL = Q * D, C = Q, CS = QP, NT = M ? 3 : 2, O = D, OUT = 0, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int t) { return (t == 2 ? 3 : t) * Q * QP * D; }
@@ -110,6 +136,9 @@ struct DT2a {
 // Transposed y, path continuing with G_z^T: t2 = B_y^T W2.
 template <int D, int Q, bool M>
 struct DT2b {
+    static constexpr int AM = 1;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int QP = pad_stride(Q);
     static constexpr int NCOL = Q * D, C = Q, CS = QP, NT = 1, O = D, OUT = D * D * QP, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 2 * Q * QP * D; }
@@ -118,6 +147,9 @@ struct DT2b {
 // Transposed z: y_E[k][n=(i,j)] = B_z^T t1 + G_z^T t2 (K-stacked), scattered to y.
 template <int D, int Q, bool M>
 struct DT3 {
+    static constexpr int AM = 1;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int QP = pad_stride(Q);
     static constexpr int NCOL = D * D, C = Q, CS = QP, NT = 2, O = D, OUT = 0, OF = NCOL, OSTR = NCOL;
     __device__ static constexpr int in_off(int t) { return t * D * D * QP; }
@@ -131,6 +163,9 @@ struct DT3 {
 // ======================================================================== mass
 template <int D, int Q>
 struct MF1 {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D);
     static constexpr int NCOL = D * D, C = D, CS = DP, NT = 1, O = Q, OUT = 0, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return 0; }
@@ -138,6 +173,9 @@ struct MF1 {
 };
 template <int D, int Q>
 struct MF2 {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D);
     static constexpr int NCOL = Q * D, C = D, CS = DP, NT = 1, O = Q, OUT = 0, OF = D, OSTR = DP;
     __device__ static constexpr int in_off(int) { return 0; }
@@ -145,6 +183,9 @@ struct MF2 {
 };
 template <int D, int Q>
 struct MF3 {
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
     static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = Q, OUT = 0, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 0; }
@@ -152,6 +193,9 @@ struct MF3 {
 };
 template <int D, int Q>
 struct MT1 {
+    static constexpr int AM = 1;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int QP = pad_stride(Q);
     static constexpr int NCOL = Q * Q, C = Q, CS = QP, NT = 1, O = D, OUT = 0, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 0; }
@@ -159,6 +203,9 @@ struct MT1 {
 };
 template <int D, int Q>
 struct MT2 {
+    static constexpr int AM = 1;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int QP = pad_stride(Q);
     static constexpr int NCOL = Q * D, C = Q, CS = QP, NT = 1, O = D, OUT = 0, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return 0; }
@@ -166,6 +213,9 @@ struct MT2 {
 };
 template <int D, int Q>
 struct MT3 {
+    static constexpr int AM = 1;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
     static constexpr int QP = pad_stride(Q);
     static constexpr int NCOL = D * D, C = Q, CS = QP, NT = 1, O = D, OUT = 0, OF = NCOL, OSTR = NCOL;
     __device__ static constexpr int in_off(int) { return 0; }

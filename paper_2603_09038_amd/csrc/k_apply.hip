@@ -134,17 +134,21 @@ __device__ __forceinline__ void load_x(T (&xv)[GroupRegs<S>::NM], const int32_t 
     for (int s = 0; s < GroupRegs<S>::NM; ++s) xv[s] = m[s] >= 0 ? x[m[s]] : T(0);
 }
 
-// One contraction pass with the chosen executor.  MFMA A-operands are read from the LDS
-// copy of the tables right before the pass (short live ranges, no hoisting across the
-// barriers); the VALU executor reads the tables with uniform loads from global memory.
-template <class P, int E, int EX, int NT, class T, class Out>
+// One contraction pass with the chosen executor.  MFMA A-operands come from the basis
+// blocks held in registers (ab, when Q is a multiple of 4) or are read from the LDS copy of
+// the tables right before the pass; the VALU executor reads the tables with uniform loads
+// from global memory.
+template <class P, int E, int EX, int NT, class T, class Out, class AB>
 __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables *stab, const DevTables *gtab,
-                                         const Out &out, int tid)
+                                         const Out &out, int tid, const AB &ab)
 {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     if constexpr (EX == EX_MFMA64) {
         double a[PassRegs<P>::RT][PassRegs<P>::KC];
-        load_a<P>(stab, a, lane);
+        if constexpr (AB::on)
+            ab.template view<P>(a);
+        else
+            load_a<P>(stab, a, lane);
         mfma_pass<P, E, NT>(in, szin, a, out, wave, lane);
     } else if constexpr (EX == EX_VALU64) {
         valu_pass<P, E, NT>(in, szin, gtab, out, tid);
@@ -191,6 +195,9 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     const int tid = threadIdx.x;
     for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
         reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
+    // (not in the matrix-free stage, whose geometry work already fills the registers)
+    ABlocks<D, Q, EX == EX_MFMA64 && Q % 4 == 0 && STAGE != 3> ab;
+    ab.load(tab, tid & 63);
 
     // Workgroup b runs on XCD b % 8.  XCD x owns the contiguous group range
     // [G x / 8, G (x+1) / 8) so neighbouring elements (sharing DOFs of x and y) meet in the
@@ -262,27 +269,27 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         // forward contractions
         if constexpr (!FWD) {
         } else if constexpr (S::kDiff) {
-            run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             lds_barrier();
             if constexpr (PAIRS) {  // the two independent y passes on one wave each
                 if (tid < 64)
-                    run_pass<DF2a<D, Q, M>, E, EX, 64>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+                    run_pass<DF2a<D, Q, M>, E, EX, 64>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
                 else
-                    run_pass<DF2b<D, Q, M>, E, EX, 64>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid - 64);
+                    run_pass<DF2b<D, Q, M>, E, EX, 64>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid - 64, ab);
             } else {
-                run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-                run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+                run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
+                run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             }
             lds_barrier();
-            run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DF3c<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
+            run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
+            run_pass<DF3c<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
         } else {
-            run_pass<MF1<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MF1<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             lds_barrier();
-            run_pass<MF2<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MF2<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             lds_barrier();
-            run_pass<MF3<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MF3<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
         }
         // the next group's map has had the forward passes to arrive: start its x gather
         T xnext[NM];
@@ -340,30 +347,30 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         // transposed contractions and scatter-add
         if constexpr (S::kDiff) {
             using CH = Chan<Q, M>;
-            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
+            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
+            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             if constexpr (M)
                 run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
-                                                                tid);
+                                                                tid, ab);
             lds_barrier();
             if constexpr (PAIRS) {
                 if (tid < 64)
-                    run_pass<DT2a<D, Q, M>, E, EX, 64>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+                    run_pass<DT2a<D, Q, M>, E, EX, 64>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
                 else
-                    run_pass<DT2b<D, Q, M>, E, EX, 64>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid - 64);
+                    run_pass<DT2b<D, Q, M>, E, EX, 64>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid - 64, ab);
             } else {
-                run_pass<DT2a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-                run_pass<DT2b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+                run_pass<DT2a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
+                run_pass<DT2b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             }
             lds_barrier();
-            run_pass<DT3<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT3<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
         } else {
-            run_pass<MT1<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MT1<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             lds_barrier();
-            run_pass<MT2<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MT2<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             lds_barrier();
-            run_pass<MT3<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MT3<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
         }
         lds_barrier();
         scatter_group<D, E, NT, S::SZ_A, ATOMIC>(bufA, lmap, y, tid);
@@ -480,6 +487,8 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
         reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
+    ABlocks<D, Q, EX == EX_MFMA64 && Q % 4 == 0> ab;
+    ab.load(tab, tid & 63);
 
     const int nb = gridDim.x;
     int g, gend, nbx;
@@ -569,20 +578,20 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
 
         // forward contractions
         if constexpr (S::kDiff) {
-            run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             lds_barrier();
-            run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
+            run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             lds_barrier();
-            run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DF3c<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
+            run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
+            run_pass<DF3c<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
         } else {
-            run_pass<MF1<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MF1<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             lds_barrier();
-            run_pass<MF2<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MF2<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             lds_barrier();
-            run_pass<MF3<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MF3<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
         }
         // D of this group, the next group's x and the map after it have landed
         dma_wait();
@@ -616,23 +625,23 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
         const int32_t *lmap = mapb[mb];
         if constexpr (S::kDiff) {
             using CH = Chan<Q, M>;
-            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
-            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
+            run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
+            run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             if constexpr (M)
                 run_pass<DT1<D, Q, M, CH::V, 3, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A},
-                                                                tid);
+                                                                tid, ab);
             lds_barrier();
-            run_pass<DT2a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
-            run_pass<DT2b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<DT2a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
+            run_pass<DT2b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             lds_barrier();
-            run_pass<DT3<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<DT3<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
         } else {
-            run_pass<MT1<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MT1<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             lds_barrier();
-            run_pass<MT2<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid);
+            run_pass<MT2<D, Q>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             lds_barrier();
-            run_pass<MT3<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid);
+            run_pass<MT3<D, Q>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
         }
         lds_barrier();
         scatter_group<D, E, NT, S::SZ_A, ATOMIC>(bufA, lmap, y, tid);
