@@ -161,41 +161,74 @@ __device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassReg
         }
 }
 
-// The 1-D basis as MFMA A-operands in registers for a whole kernel (FP64 MFMA executor,
-// Q a multiple of 4).  Every pass matrix is then a set of 4x4 tiles of one of two blocks
-//   F = [B; G]      rows o < Q: B[o][k], o >= Q: G[o-Q][k]; k < D (forward passes),
-//   T = [B^T G^T]   rows o < D; k < Q: B[k][o], k >= Q: G[k-Q][o] (transposed passes),
-// at whole tiles (pass row tile rt is block tile amrt(rt), k chunk kc is amkc(kc)), so the
-// tables are read once per kernel instead of once per pass and wave: at p = 6 that removes
-// about 60 % of the kernel's LDS instructions.  Lane l holds A[4 rt + (l & 3)][4 kc + (l >> 4)]
-// as in load_a; the values, and so the results, are those of the per-pass loads.
+// The 1-D basis as MFMA A-operands in registers (FP64 MFMA executor).  Most pass matrices
+// are whole 4x4 tiles of one of two blocks
+//   F = [B; G]      rows o < Q: B[o][k], Q <= o < 2Q: G[o-Q][k]; k < D (forward passes),
+//   T = [B^T G^T]   rows o < D; k < Q: B[k][o], Q <= k < 2Q: G[k-Q][o] (transposed passes)
+// (pass row tile rt is block tile amrt(rt), k chunk kc is amkc(kc); passes with AV false,
+// the G-only ones when Q is not a multiple of 4, read their tiles from the LDS tables as
+// before).  With Q a multiple of 4 (and at p <= 6 generally) both blocks stay in registers
+// for the whole kernel; at larger p they would not fit beside the rest, so F is read from
+// the LDS tables at the start of each group's forward passes and T at the start of its
+// transposed ones.  Either way the tables are read once per group and wave instead of once
+// per pass: at p = 6 that removes about 60 % of the kernel's LDS instructions.  Lane l
+// holds A[4 rt + (l & 3)][4 kc + (l >> 4)] as in load_a, so the results are those of the
+// per-pass loads.
 template <int D, int Q, bool ON>
 struct ABlocks {
     static constexpr bool on = ON;
-    static constexpr int QT = Q / 4;
-    static constexpr int RTF = ON ? 2 * QT : 1, KCF = ON ? (D + 3) / 4 : 1;
-    static constexpr int RTT = ON ? (D + 3) / 4 : 1, KCT = ON ? 2 * QT : 1;
+    static constexpr int RTF = ON ? (2 * Q + 3) / 4 : 1, KCF = ON ? (D + 3) / 4 : 1;
+    static constexpr int RTT = ON ? (D + 3) / 4 : 1, KCT = ON ? (2 * Q + 3) / 4 : 1;
+    // both blocks for the whole kernel, or each for its half of every group
+    static constexpr bool WHOLE = RTF * KCF + RTT * KCT <= 16;
     double f[RTF][KCF], t[RTT][KCT];
-    __device__ __forceinline__ void load(const DevTables *tab, int lane)
+    __device__ __forceinline__ void load_f(const DevTables *tab, int lane)
     {
         if constexpr (ON) {
-            static_assert(Q % 4 == 0, "block tiles must not straddle the B / G boundary");
             const int r = lane & 3, c = lane >> 4;
 #pragma unroll
             for (int rt = 0; rt < RTF; ++rt)
 #pragma unroll
                 for (int kc = 0; kc < KCF; ++kc) {
                     const int o = 4 * rt + r, k = 4 * kc + c;
-                    f[rt][kc] = k < D ? (o < Q ? tB(tab, o, k, D) : tG(tab, o - Q, k, D)) : 0.0;
+                    const bool ok = k < D && o < 2 * Q;
+                    const int ob = ok ? (o < Q ? o : o - Q) : 0, kk = ok ? k : 0;
+                    const double v = o < Q ? tB(tab, ob, kk, D) : tG(tab, ob, kk, D);
+                    f[rt][kc] = ok ? v : 0.0;
                 }
+        }
+    }
+    __device__ __forceinline__ void load_t(const DevTables *tab, int lane)
+    {
+        if constexpr (ON) {
+            const int r = lane & 3, c = lane >> 4;
 #pragma unroll
             for (int rt = 0; rt < RTT; ++rt)
 #pragma unroll
                 for (int kc = 0; kc < KCT; ++kc) {
                     const int o = 4 * rt + r, k = 4 * kc + c;
-                    t[rt][kc] = o < D ? (k < Q ? tB(tab, k, o, D) : tG(tab, k - Q, o, D)) : 0.0;
+                    const bool ok = o < D && k < 2 * Q;
+                    const int kb = ok ? (k < Q ? k : k - Q) : 0, oo = ok ? o : 0;
+                    const double v = k < Q ? tB(tab, kb, oo, D) : tG(tab, kb, oo, D);
+                    t[rt][kc] = ok ? v : 0.0;
                 }
         }
+    }
+    // once per kernel (WHOLE) or at the start of each group's forward / transposed passes
+    __device__ __forceinline__ void kernel_start(const DevTables *tab, int lane)
+    {
+        if constexpr (ON && WHOLE) {
+            load_f(tab, lane);
+            load_t(tab, lane);
+        }
+    }
+    __device__ __forceinline__ void forward_start(const DevTables *tab, int lane)
+    {
+        if constexpr (ON && !WHOLE) load_f(tab, lane);
+    }
+    __device__ __forceinline__ void transposed_start(const DevTables *tab, int lane)
+    {
+        if constexpr (ON && !WHOLE) load_t(tab, lane);
     }
     // the A-operand tiles of pass P
     template <class P>
@@ -282,11 +315,15 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
             eS[bi] = e;
             n0S[bi] = n0;
             cv[bi] = tv && (n0 + nl < P::NCOL);
-            // no masking needed: past K a lane reads a finite value of its own column
-            // (A is zero there); padding columns are independent and never stored
+            // past K a lane reads a value of its own column and zeroes it (a pass that takes
+            // its A tiles from a basis block may see nonzero A there); padding columns are
+            // independent and never stored
             const double *base = in + e * szin + n0 * CS;
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) bv[bi][kc] = base[lin[kc]];
+            for (int kc = 0; kc < KC; ++kc) {
+                const double v = base[lin[kc]];
+                bv[bi][kc] = kval[kc] ? v : 0.0;
+            }
         }
         double acc[BATCH][RT];
 #pragma unroll

@@ -13,8 +13,11 @@
 //   A(tab,o,k) the stacked pass matrix (k = t C + c),
 //   OUT        offset of the output inside the element's output region: Out[o][n] is
 //              stored at OUT + n + NCOL o,
-//   AM, amrt, amkc  where the pass's MFMA A-operand tiles sit in the two basis blocks that
-//              ABlocks keeps in registers (used when Q is a multiple of 4).
+//   AV, AM, amrt, amkc  whether the pass's MFMA A-operand tiles are whole 4x4 tiles of one
+//              of the two basis blocks that ABlocks keeps in registers, which block, and
+//              where (B-only row tiles may run past row Q into the G rows when Q is not a
+//              multiple of 4: those rows are computed and never stored; B^T-only k chunks
+//              may run into the G^T columns: the pass zeroes its B-operand past K).
 // Because each stage stores its output as [o][n], the next stage's contracted index is
 // the fastest one in memory (the cyclic index order of the paper's Sec. III-D), and a
 // block of rows of one pass (e.g. its G rows) is itself a contiguous tensor.
@@ -39,6 +42,7 @@ struct Chan {
 // Forward x: X[n=(j,k)][i] -> U1[o1][n]: rows o1 < Q are B_x X (BX), rows >= Q are G_x X (GX).
 template <int D, int Q, bool M>
 struct DF1 {
+    static constexpr bool AV = true;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -50,6 +54,7 @@ struct DF1 {
 // Forward y on BX: BX[n=(k,a)][j] -> rows o2 < Q: T_BB = B_y BX, rows >= Q: T_BG = G_y BX.
 template <int D, int Q, bool M>
 struct DF2a {
+    static constexpr bool AV = true;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -61,6 +66,7 @@ struct DF2a {
 // Forward y on GX: T_GB = B_y GX.
 template <int D, int Q, bool M>
 struct DF2b {
+    static constexpr bool AV = true;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -72,6 +78,7 @@ struct DF2b {
 // Forward z on T_BB[n=(a,b)][k]: dz = G_z T_BB (and u = B_z T_BB, stacked first, with mass).
 template <int D, int Q, bool M>
 struct DF3a {
+    static constexpr bool AV = M || Q % 4 == 0;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return M ? rt : rt + Q / 4; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -87,6 +94,7 @@ struct DF3a {
 // Forward z on T_BG: dy = B_z T_BG.
 template <int D, int Q, bool M>
 struct DF3b {
+    static constexpr bool AV = true;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -98,6 +106,7 @@ struct DF3b {
 // Forward z on T_GB: dx = B_z T_GB.
 template <int D, int Q, bool M>
 struct DF3c {
+    static constexpr bool AV = true;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -109,6 +118,7 @@ struct DF3c {
 // Transposed x of one channel: V_ch[n=(b,c)][a] -> W_slot[i][n] with G^T (dx) or B^T.
 template <int D, int Q, bool M, int CH_OFF, int SLOT, bool GT>
 struct DT1 {
+    static constexpr bool AV = !GT || Q % 4 == 0;
     static constexpr int AM = 1;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return GT ? kc + Q / 4 : kc; }
@@ -121,9 +131,12 @@ struct DT1 {
 // Transposed y, path continuing with B_z^T: t1 = B_y^T W0 + G_y^T W1 (+ B_y^T W3).
 template <int D, int Q, bool M>
 struct DT2a {
+    static constexpr bool AV = !M || Q % 4 == 0;
     static constexpr int AM = 1;
     __device__ static constexpr int amrt(int rt) { return rt; }
-    __device__ static constexpr int amkc(int kc) { return kc % (Q / 4) + (kc / (Q / 4) == 1 ? Q / 4 : 0); }
+    // tensors 0, 1 are the B^T, G^T halves of the block; the third (mass, Q a multiple of 4)
+    // reuses the B^T half
+    __device__ static constexpr int amkc(int kc) { return M ? kc % (Q / 4) + (kc / (Q / 4) == 1 ? Q / 4 : 0) : kc; }
     static constexpr int QP = pad_stride(Q);
     static constexpr int NCOL = Q * D, C = Q, CS = QP, NT = M ? 3 : 2, O = D, OUT = 0, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int t) { return (t == 2 ? 3 : t) * Q * QP * D; }
@@ -136,6 +149,7 @@ struct DT2a {
 // Transposed y, path continuing with G_z^T: t2 = B_y^T W2.
 template <int D, int Q, bool M>
 struct DT2b {
+    static constexpr bool AV = true;
     static constexpr int AM = 1;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -147,6 +161,7 @@ struct DT2b {
 // Transposed z: y_E[k][n=(i,j)] = B_z^T t1 + G_z^T t2 (K-stacked), scattered to y.
 template <int D, int Q, bool M>
 struct DT3 {
+    static constexpr bool AV = true;
     static constexpr int AM = 1;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -163,6 +178,7 @@ struct DT3 {
 // ======================================================================== mass
 template <int D, int Q>
 struct MF1 {
+    static constexpr bool AV = true;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -173,6 +189,7 @@ struct MF1 {
 };
 template <int D, int Q>
 struct MF2 {
+    static constexpr bool AV = true;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -183,6 +200,7 @@ struct MF2 {
 };
 template <int D, int Q>
 struct MF3 {
+    static constexpr bool AV = true;
     static constexpr int AM = 0;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -193,6 +211,7 @@ struct MF3 {
 };
 template <int D, int Q>
 struct MT1 {
+    static constexpr bool AV = true;
     static constexpr int AM = 1;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -203,6 +222,7 @@ struct MT1 {
 };
 template <int D, int Q>
 struct MT2 {
+    static constexpr bool AV = true;
     static constexpr int AM = 1;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }
@@ -213,6 +233,7 @@ struct MT2 {
 };
 template <int D, int Q>
 struct MT3 {
+    static constexpr bool AV = true;
     static constexpr int AM = 1;
     __device__ static constexpr int amrt(int rt) { return rt; }
     __device__ static constexpr int amkc(int kc) { return kc; }

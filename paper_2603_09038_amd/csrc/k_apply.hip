@@ -145,7 +145,7 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     if constexpr (EX == EX_MFMA64) {
         double a[PassRegs<P>::RT][PassRegs<P>::KC];
-        if constexpr (AB::on)
+        if constexpr (AB::on && P::AV)
             ab.template view<P>(a);
         else
             load_a<P>(stab, a, lane);
@@ -158,6 +158,16 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
         load_a16<P, BF>(stab, a, lane);
         mfma16_pass<P, E, NT, BF>(in, szin, a, out, wave, lane);
     }
+}
+
+// Basis blocks in registers (ABlocks): always when both fit for the whole kernel; for
+// larger orders, loaded per half group, only for the mass operator (the diffusion kernels
+// at p >= 7 then exceed 128 registers and lose a wave per SIMD: p = 8 1.32 -> 1.48 ms,
+// against 0.55 -> 0.535 ms for mass).
+template <int D, int Q, int OPS>
+constexpr bool ablocks_on()
+{
+    return ABlocks<D, Q, true>::WHOLE || (OPS & 2) == 0;
 }
 
 // STAGE 0: the fused apply.  The unfused apply (the paper's baseline that fusion is
@@ -196,8 +206,8 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
         reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
     // (not in the matrix-free stage, whose geometry work already fills the registers)
-    ABlocks<D, Q, EX == EX_MFMA64 && Q % 4 == 0 && STAGE != 3> ab;
-    ab.load(tab, tid & 63);
+    ABlocks<D, Q, EX == EX_MFMA64 && STAGE != 3 && ablocks_on<D, Q, OPS>()> ab;
+    ab.kernel_start(tab, tid & 63);
 
     // Workgroup b runs on XCD b % 8.  XCD x owns the contiguous group range
     // [G x / 8, G (x+1) / 8) so neighbouring elements (sharing DOFs of x and y) meet in the
@@ -267,6 +277,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         if constexpr (CENTRE && FWD) centre_tiles<S, E, NT>(bufA, emean, tid);
 
         // forward contractions
+        ab.forward_start(&stab, tid & 63);
         if constexpr (!FWD) {
         } else if constexpr (S::kDiff) {
             run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
@@ -345,6 +356,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         lds_barrier();
 
         // transposed contractions and scatter-add
+        ab.transposed_start(&stab, tid & 63);
         if constexpr (S::kDiff) {
             using CH = Chan<Q, M>;
             run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
@@ -487,8 +499,8 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
         reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
-    ABlocks<D, Q, EX == EX_MFMA64 && Q % 4 == 0> ab;
-    ab.load(tab, tid & 63);
+    ABlocks<D, Q, EX == EX_MFMA64 && ablocks_on<D, Q, OPS>()> ab;
+    ab.kernel_start(tab, tid & 63);
 
     const int nb = gridDim.x;
     int g, gend, nbx;
@@ -577,6 +589,7 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
         if constexpr (CENTRE) centre_tiles<S, E, NT>(bufA, emean, tid);
 
         // forward contractions
+        ab.forward_start(&stab, tid & 63);
         if constexpr (S::kDiff) {
             run_pass<DF1<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             lds_barrier();
@@ -622,6 +635,7 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
         if (more) issue_d(gn);
 
         // transposed contractions and scatter-add
+        ab.transposed_start(&stab, tid & 63);
         const int32_t *lmap = mapb[mb];
         if constexpr (S::kDiff) {
             using CH = Chan<Q, M>;
