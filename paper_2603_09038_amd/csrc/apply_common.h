@@ -460,6 +460,79 @@ __device__ __forceinline__ void load_a16(const DevTables *tab,
         }
 }
 
+// The same basis blocks F = [B; G] and T = [B^T G^T] as 16x16 A-operand tiles of the
+// 16-bit MFMA, packed once per kernel (a few registers per block).  A pass uses them when
+// its matrix is the leading rows and columns of a block (B-only row blocks run into unstored
+// G rows, B^T-only k blocks into zeroed B-operand columns); the others (G-only, and the
+// third tensor of the mass term's K-stacked pass) pack their tiles per pass as before.
+template <int D, int Q, bool BF, bool ON>
+struct ABlocks16 {
+    using V = typename Mfma16<BF>::V;
+    static constexpr bool on = ON;
+    static constexpr int RBF = ON ? (2 * Q + 15) / 16 : 1, KCF = ON ? (D + 15) / 16 : 1;
+    static constexpr int RBT = ON ? (D + 15) / 16 : 1, KCT = ON ? (2 * Q + 15) / 16 : 1;
+    V f[RBF][KCF], t[RBT][KCT];
+    __device__ __forceinline__ void load(const DevTables *tab, int lane)
+    {
+        if constexpr (ON) {
+#pragma unroll
+            for (int rb = 0; rb < RBF; ++rb)
+#pragma unroll
+                for (int kc = 0; kc < KCF; ++kc) {
+                    float v4[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int o = 16 * rb + (lane & 15), k = 16 * kc + 4 * (lane >> 4) + u;
+                        const bool ok = k < D && o < 2 * Q;
+                        const int ob = ok ? (o < Q ? o : o - Q) : 0, kk = ok ? k : 0;
+                        const double v = o < Q ? tB(tab, ob, kk, D) : tG(tab, ob, kk, D);
+                        v4[u] = ok ? (float)v : 0.0f;
+                    }
+                    f[rb][kc] = Mfma16<BF>::pack(v4);
+                }
+#pragma unroll
+            for (int rb = 0; rb < RBT; ++rb)
+#pragma unroll
+                for (int kc = 0; kc < KCT; ++kc) {
+                    float v4[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int o = 16 * rb + (lane & 15), k = 16 * kc + 4 * (lane >> 4) + u;
+                        const bool ok = o < D && k < 2 * Q;
+                        const int kb = ok ? (k < Q ? k : k - Q) : 0, oo = ok ? o : 0;
+                        const double v = k < Q ? tB(tab, kb, oo, D) : tG(tab, kb, oo, D);
+                        v4[u] = ok ? (float)v : 0.0f;
+                    }
+                    t[rb][kc] = Mfma16<BF>::pack(v4);
+                }
+        }
+    }
+    __device__ __forceinline__ void kernel_start(const DevTables *tab, int lane) { load(tab, lane); }
+    __device__ __forceinline__ void forward_start(const DevTables *, int) {}
+    __device__ __forceinline__ void transposed_start(const DevTables *, int) {}
+    // pass P's matrix is the leading rows and columns of its block
+    template <class P>
+    static constexpr bool leading()
+    {
+        if (!P::AV) return false;
+        for (int i = 0; i < 16; ++i)
+            if (P::amrt(i) != i || P::amkc(i) != i) return false;
+        return true;
+    }
+    template <class P>
+    __device__ __forceinline__ void view(V (&a)[PassRegs16<P>::RB][PassRegs16<P>::KC]) const
+    {
+#pragma unroll
+        for (int rb = 0; rb < PassRegs16<P>::RB; ++rb)
+#pragma unroll
+            for (int kc = 0; kc < PassRegs16<P>::KC; ++kc)
+                if constexpr (P::AM == 0)
+                    a[rb][kc] = f[rb][kc];
+                else
+                    a[rb][kc] = t[rb][kc];
+    }
+};
+
 template <class P, int E, int NT, bool BF, class Out>
 __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
                                             const typename Mfma16<BF>::V (&a)[PassRegs16<P>::RB][PassRegs16<P>::KC],
@@ -502,7 +575,10 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
             for (int kc = 0; kc < KC; ++kc) {
                 float f[4];
 #pragma unroll
-                for (int t4 = 0; t4 < 4; ++t4) f[t4] = base[lin[kc][t4]];
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const float v = base[lin[kc][t4]];
+                    f[t4] = kval[kc][t4] ? v : 0.0f;
+                }
                 bv[bi][kc] = Mfma16<BF>::pack(f);
             }
         }

@@ -155,7 +155,10 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
     } else {
         constexpr bool BF = EX == EX_MFMA16B;
         typename Mfma16<BF>::V a[PassRegs16<P>::RB][PassRegs16<P>::KC];
-        load_a16<P, BF>(stab, a, lane);
+        if constexpr (AB::on && AB::template leading<P>())
+            ab.template view<P>(a);
+        else
+            load_a16<P, BF>(stab, a, lane);
         mfma16_pass<P, E, NT, BF>(in, szin, a, out, wave, lane);
     }
 }
@@ -169,6 +172,12 @@ constexpr bool ablocks_on()
 {
     return ABlocks<D, Q, true>::WHOLE || (OPS & 2) == 0;
 }
+// the block type of an executor: FP64 tiles, 16-bit tiles (always small), or none (VALU)
+template <int D, int Q, int OPS, int EX, bool ON>
+using ABlocksFor = typename std::conditional<
+    EX == EX_MFMA64, ABlocks<D, Q, ON && ablocks_on<D, Q, OPS>()>,
+    typename std::conditional<(EX >= EX_MFMA16F), ABlocks16<D, Q, EX == EX_MFMA16B, ON>,
+                              ABlocks<D, Q, false>>::type>::type;
 
 // STAGE 0: the fused apply.  The unfused apply (the paper's baseline that fusion is
 // measured against) runs the same code in three launches through HBM: STAGE 1 gathers x,
@@ -206,7 +215,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
         reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
     // (not in the matrix-free stage, whose geometry work already fills the registers)
-    ABlocks<D, Q, EX == EX_MFMA64 && STAGE != 3 && ablocks_on<D, Q, OPS>()> ab;
+    ABlocksFor<D, Q, OPS, EX, STAGE != 3> ab;
     ab.kernel_start(tab, tid & 63);
 
     // Workgroup b runs on XCD b % 8.  XCD x owns the contiguous group range
@@ -499,7 +508,7 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int i = tid; i < (int)(sizeof(DevTables) / sizeof(double)); i += NT)
         reinterpret_cast<double *>(&stab)[i] = reinterpret_cast<const double *>(tab)[i];
-    ABlocks<D, Q, EX == EX_MFMA64 && ablocks_on<D, Q, OPS>()> ab;
+    ABlocksFor<D, Q, OPS, EX, true> ab;
     ab.kernel_start(tab, tid & 63);
 
     const int nb = gridDim.x;
