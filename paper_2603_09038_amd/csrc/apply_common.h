@@ -139,9 +139,21 @@ __device__ __forceinline__ double tG(const DevTables *t, int a, int i, int D) { 
 // slice: column n = l & 15, contracted index k = l >> 4, output row l >> 4.  On gfx950
 // this shape sustains ~1.4x the FP64 rate of v_mfma_f64_16x16x4f64 and pads the small
 // 1-D dimensions (d = p+1, Q) to multiples of 4 instead of 16.
+// Optional members of a "wide" pass (one that takes a whole basis block although it needs
+// only part of it): KREG register k length, ROFF the first register row it stores and OS how
+// many, KOFF the register k of its first input column and KS how many input columns.
+template <class P, class = void>
+struct PassX {
+    static constexpr int KREG = P::NT * P::C, ROFF = 0, OS = P::O, KOFF = 0, KS = P::NT * P::C;
+};
+template <class P>
+struct PassX<P, std::void_t<decltype(P::KREG)>> {
+    static constexpr int KREG = P::KREG, ROFF = P::ROFF, OS = P::OS, KOFF = P::KOFF, KS = P::KS;
+};
+
 template <class P>
 struct PassRegs {
-    static constexpr int K = P::NT * P::C;
+    static constexpr int K = PassX<P>::KREG;
     static constexpr int KC = (K + 3) / 4;   // k chunks of 4
     static constexpr int RT = (P::O + 3) / 4;  // 4-row tiles
 };
@@ -176,7 +188,7 @@ __device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassReg
 // per-pass loads.
 template <int D, int Q, bool ON>
 struct ABlocks {
-    static constexpr bool on = ON;
+    static constexpr bool on = ON, wide_ok = ON;
     static constexpr int RTF = ON ? (2 * Q + 3) / 4 : 1, KCF = ON ? (D + 3) / 4 : 1;
     static constexpr int RTT = ON ? (D + 3) / 4 : 1, KCT = ON ? (2 * Q + 3) / 4 : 1;
     // both blocks for the whole kernel, or each for its half of every group
@@ -291,16 +303,18 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
     constexpr int BATCH = NR < kMfmaBatch ? NR : kMfmaBatch;
     const int kl = lane >> 4, nl = lane & 15;
     // lane constants: B-operand offsets per k chunk, output offset of row kl
+    constexpr int KOFF = PassX<P>::KOFF, KS = PassX<P>::KS, ROFF = PassX<P>::ROFF, OS = PassX<P>::OS;
     int lin[KC];
     bool kval[KC];
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
-        const int k = 4 * kc + kl;
-        kval[kc] = k < K;
-        const int t = k / C, c = k - t * C;
+        const int k = 4 * kc + kl - KOFF;  // input column of register k
+        kval[kc] = k >= 0 && k < KS;
+        const int kk = kval[kc] ? k : 0;
+        const int t = kk / C, c = kk - t * C;
         lin[kc] = nl * CS + (kval[kc] ? P::in_off(t) + c : 0);
     }
-    const int lout = P::OUT + NCOLO * kl;
+    const int lout = P::OUT + NCOLO * (kl - ROFF);
 #pragma unroll 1
     for (int r0 = 0; r0 < NR; r0 += BATCH) {
         double bv[BATCH][KC];
@@ -343,7 +357,7 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
             const int ob = lout + OutLayout<P>::opos(n0S[bi] + nl);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
-                if (4 * rt + kl < P::O) out.put(eS[bi], ob + 4 * rt * NCOLO, acc[bi][rt]);
+                if (4 * rt + kl >= ROFF && 4 * rt + kl < ROFF + OS) out.put(eS[bi], ob + 4 * rt * NCOLO, acc[bi][rt]);
         }
     }
 }
@@ -354,6 +368,7 @@ __device__ __forceinline__ void mfma_pass(const double *in, int szin,
 template <class P, int E, int NTH, class Out>
 __device__ __forceinline__ void valu_pass(const double *in, int szin, const DevTables *tab, const Out &out, int tid)
 {
+    static_assert(PassX<P>::KOFF == 0 && PassX<P>::ROFF == 0, "wide passes are FP64 MFMA only");
     constexpr int C = P::C, CS = P::CS, NT = P::NT, O = P::O, NCOLO = OutLayout<P>::NCOLO;
     constexpr int NCOLS = E * P::NCOL;
     constexpr int NR = (NCOLS + NTH - 1) / NTH;
@@ -468,7 +483,7 @@ __device__ __forceinline__ void load_a16(const DevTables *tab,
 template <int D, int Q, bool BF, bool ON>
 struct ABlocks16 {
     using V = typename Mfma16<BF>::V;
-    static constexpr bool on = ON;
+    static constexpr bool on = ON, wide_ok = false;
     static constexpr int RBF = ON ? (2 * Q + 15) / 16 : 1, KCF = ON ? (D + 15) / 16 : 1;
     static constexpr int RBT = ON ? (D + 15) / 16 : 1, KCT = ON ? (2 * Q + 15) / 16 : 1;
     V f[RBF][KCF], t[RBT][KCT];
@@ -539,6 +554,7 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
                                             const Out &out, int wave, int lane)
 {
     using V = typename Mfma16<BF>::V;
+    static_assert(PassX<P>::KOFF == 0 && PassX<P>::ROFF == 0, "wide passes are FP64 MFMA only");
     constexpr int C = P::C, CS = P::CS, K = PassRegs16<P>::K, KC = PassRegs16<P>::KC, RB = PassRegs16<P>::RB;
     constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE, NW = NT / 64, NCOLO = OutLayout<P>::NCOLO;
     constexpr int NR = (NTILE + NW - 1) / NW;

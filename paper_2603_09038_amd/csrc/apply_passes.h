@@ -115,6 +115,23 @@ struct DF3c {
     __device__ static constexpr int in_off(int) { return 2 * Q * Q * DP; }
     __device__ static double A(const DevTables *t, int o, int k) { return tB(t, o, k, D); }
 };
+// DF3a without the mass term as a wide pass on the whole [B; G] block (when Q is not a
+// multiple of 4 its G rows do not start on a 4-row tile): rows 0..2Q-1 are computed, the G
+// rows Q..2Q-1 stored as dz.
+template <int D, int Q, bool M>
+struct DF3aW {
+    static_assert(!M, "with the mass term DF3a already takes the whole block");
+    static constexpr bool AV = true;
+    static constexpr int AM = 0;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
+    static constexpr int DP = pad_stride(D), QP = pad_stride(Q);
+    static constexpr int NCOL = Q * Q, C = D, CS = DP, NT = 1, O = 2 * Q, OUT = Chan<Q, M>::Z;
+    static constexpr int OF = Q, OSTR = QP;
+    static constexpr int KREG = D, ROFF = Q, OS = Q, KOFF = 0, KS = D;
+    __device__ static constexpr int in_off(int) { return 0; }
+    __device__ static double A(const DevTables *t, int o, int k) { return o < Q ? tB(t, o, k, D) : tG(t, o - Q, k, D); }
+};
 // Transposed x of one channel: V_ch[n=(b,c)][a] -> W_slot[i][n] with G^T (dx) or B^T.
 template <int D, int Q, bool M, int CH_OFF, int SLOT, bool GT>
 struct DT1 {
@@ -126,6 +143,21 @@ struct DT1 {
     static constexpr int NCOL = Q * Q, C = Q, CS = QP, NT = 1, O = D, OUT = SLOT * Q * QP * D, OF = Q, OSTR = QP;
     __device__ static constexpr int in_off(int) { return CH_OFF; }
     __device__ static double A(const DevTables *t, int o, int k) { return GT ? tG(t, k, o, D) : tB(t, k, o, D); }
+};
+// DT1 with G^T as a wide pass on the whole [B^T G^T] block (when Q is not a multiple of 4 its
+// G^T columns do not start on a 4-column chunk): register k Q..2Q-1 carry the channel, the
+// B^T columns multiply zeros.
+template <int D, int Q, bool M, int CH_OFF, int SLOT>
+struct DT1W {
+    static constexpr bool AV = true;
+    static constexpr int AM = 1;
+    __device__ static constexpr int amrt(int rt) { return rt; }
+    __device__ static constexpr int amkc(int kc) { return kc; }
+    static constexpr int QP = pad_stride(Q);
+    static constexpr int NCOL = Q * Q, C = Q, CS = QP, NT = 1, O = D, OUT = SLOT * Q * QP * D, OF = Q, OSTR = QP;
+    static constexpr int KREG = 2 * Q, ROFF = 0, OS = D, KOFF = Q, KS = Q;
+    __device__ static constexpr int in_off(int) { return CH_OFF; }
+    __device__ static double A(const DevTables *t, int o, int k) { return k < Q ? tB(t, k, o, D) : tG(t, k - Q, o, D); }
 };
 // W slots in buffer A: 0 = dx, 1 = dy, 2 = dz, 3 = u.
 // Transposed y, path continuing with B_z^T: t1 = B_y^T W0 + G_y^T W1 (+ B_y^T W3).

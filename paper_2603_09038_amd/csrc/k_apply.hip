@@ -163,15 +163,20 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
     }
 }
 
-// Basis blocks in registers (ABlocks): always when both fit for the whole kernel; for
-// larger orders, loaded per half group, only for the mass operator (the diffusion kernels
-// at p >= 7 then exceed 128 registers and lose a wave per SIMD: p = 8 1.32 -> 1.48 ms,
-// against 0.55 -> 0.535 ms for mass).
+// Basis blocks in registers (ABlocks): both for the whole kernel where they fit, else each
+// for its half of every group.  The two passes whose matrix does not start on a whole tile
+// of a block when Q is not a multiple of 4 (dz forward, dx transposed) then run as wide
+// passes on the whole block, so no pass keeps tiles of its own beside the block (with per-
+// pass tiles beside it the p = 8 diffusion kernel needed 144 registers and lost a wave per
+// SIMD: 1.32 -> 1.48 ms).
 template <int D, int Q, int OPS>
 constexpr bool ablocks_on()
 {
-    return ABlocks<D, Q, true>::WHOLE || (OPS & 2) == 0;
+    return true;
 }
+// the pass to run: its wide form when it takes its tiles from a block it does not start on
+template <class AB, class P, class PW>
+using WideIf = typename std::conditional<AB::wide_ok && !P::AV, PW, P>::type;
 // the block type of an executor: FP64 tiles, 16-bit tiles (always small), or none (VALU)
 template <int D, int Q, int OPS, int EX, bool ON>
 using ABlocksFor = typename std::conditional<
@@ -301,7 +306,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
                 run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             }
             lds_barrier();
-            run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
+            run_pass<WideIf<decltype(ab), DF3a<D, Q, M>, DF3aW<D, Q, M>>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             run_pass<DF3c<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
         } else {
@@ -368,7 +373,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
         ab.transposed_start(&stab, tid & 63);
         if constexpr (S::kDiff) {
             using CH = Chan<Q, M>;
-            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
+            run_pass<WideIf<decltype(ab), DT1<D, Q, M, CH::X, 0, true>, DT1W<D, Q, M, CH::X, 0>>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             if constexpr (M)
@@ -605,7 +610,7 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
             run_pass<DF2a<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             run_pass<DF2b<D, Q, M>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             lds_barrier();
-            run_pass<DF3a<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
+            run_pass<WideIf<decltype(ab), DF3a<D, Q, M>, DF3aW<D, Q, M>>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             run_pass<DF3b<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
             run_pass<DF3c<D, Q, M>, E, EX, NT>(bufA, S::SZ_A, &stab, tab, LdsOut<T>{bufB, S::SZ_B}, tid, ab);
         } else {
@@ -648,7 +653,7 @@ __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
         const int32_t *lmap = mapb[mb];
         if constexpr (S::kDiff) {
             using CH = Chan<Q, M>;
-            run_pass<DT1<D, Q, M, CH::X, 0, true>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
+            run_pass<WideIf<decltype(ab), DT1<D, Q, M, CH::X, 0, true>, DT1W<D, Q, M, CH::X, 0>>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             run_pass<DT1<D, Q, M, CH::Y, 1, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             run_pass<DT1<D, Q, M, CH::Z, 2, false>, E, EX, NT>(bufB, S::SZ_B, &stab, tab, LdsOut<T>{bufA, S::SZ_A}, tid, ab);
             if constexpr (M)
