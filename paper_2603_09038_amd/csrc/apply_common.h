@@ -242,6 +242,12 @@ struct ABlocks {
     {
         if constexpr (ON && !WHOLE) load_t(tab, lane);
     }
+    // pass P takes its tiles from a block
+    template <class P>
+    static constexpr bool direct()
+    {
+        return P::AV;
+    }
     // the A-operand tiles of pass P
     template <class P>
     __device__ __forceinline__ void view(double (&a)[PassRegs<P>::RT][PassRegs<P>::KC]) const
@@ -450,7 +456,7 @@ struct Mfma16 {
 
 template <class P>
 struct PassRegs16 {
-    static constexpr int K = P::NT * P::C;
+    static constexpr int K = PassX<P>::KREG;
     static constexpr int KC = (K + 15) / 16;   // k chunks of 16
     static constexpr int RB = (P::O + 15) / 16;  // 16-row blocks
 };
@@ -483,7 +489,7 @@ __device__ __forceinline__ void load_a16(const DevTables *tab,
 template <int D, int Q, bool BF, bool ON>
 struct ABlocks16 {
     using V = typename Mfma16<BF>::V;
-    static constexpr bool on = ON, wide_ok = false;
+    static constexpr bool on = ON, wide_ok = ON;
     static constexpr int RBF = ON ? (2 * Q + 15) / 16 : 1, KCF = ON ? (D + 15) / 16 : 1;
     static constexpr int RBT = ON ? (D + 15) / 16 : 1, KCT = ON ? (2 * Q + 15) / 16 : 1;
     V f[RBF][KCF], t[RBT][KCT];
@@ -535,6 +541,11 @@ struct ABlocks16 {
         return true;
     }
     template <class P>
+    static constexpr bool direct()
+    {
+        return leading<P>();
+    }
+    template <class P>
     __device__ __forceinline__ void view(V (&a)[PassRegs16<P>::RB][PassRegs16<P>::KC]) const
     {
 #pragma unroll
@@ -554,8 +565,8 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
                                             const Out &out, int wave, int lane)
 {
     using V = typename Mfma16<BF>::V;
-    static_assert(PassX<P>::KOFF == 0 && PassX<P>::ROFF == 0, "wide passes are FP64 MFMA only");
-    constexpr int C = P::C, CS = P::CS, K = PassRegs16<P>::K, KC = PassRegs16<P>::KC, RB = PassRegs16<P>::RB;
+    constexpr int C = P::C, CS = P::CS, KC = PassRegs16<P>::KC, RB = PassRegs16<P>::RB;
+    constexpr int KOFF = PassX<P>::KOFF, KS = PassX<P>::KS, ROFF = PassX<P>::ROFF, OS = PassX<P>::OS;
     constexpr int TPE = Tiling<P>::TPE, NTILE = E * TPE, NW = NT / 64, NCOLO = OutLayout<P>::NCOLO;
     constexpr int NR = (NTILE + NW - 1) / NW;
     constexpr int BATCH = NR < kMfmaBatch ? NR : kMfmaBatch;
@@ -566,12 +577,13 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
     for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int k = 16 * kc + 4 * kl + t;
-            kval[kc][t] = k < K;
-            const int tt = k / C, c = k - tt * C;
+            const int k = 16 * kc + 4 * kl + t - KOFF;  // input column of register k
+            kval[kc][t] = k >= 0 && k < KS;
+            const int kk = kval[kc][t] ? k : 0;
+            const int tt = kk / C, c = kk - tt * C;
             lin[kc][t] = nl * CS + (kval[kc][t] ? P::in_off(tt) + c : 0);
         }
-    const int lout = P::OUT + NCOLO * 4 * kl;
+    const int lout = P::OUT + NCOLO * (4 * kl - ROFF);
 #pragma unroll 1
     for (int r0 = 0; r0 < NR; r0 += BATCH) {
         V bv[BATCH][KC];
@@ -617,7 +629,8 @@ __device__ __forceinline__ void mfma16_pass(const float *in, int szin,
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    if (16 * rb + 4 * kl + v < P::O) out.put(eS[bi], ob + NCOLO * (16 * rb + v), acc[bi][rb][v]);
+                    if (16 * rb + 4 * kl + v >= ROFF && 16 * rb + 4 * kl + v < ROFF + OS)
+                        out.put(eS[bi], ob + NCOLO * (16 * rb + v), acc[bi][rb][v]);
         }
     }
 }

@@ -145,7 +145,7 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     if constexpr (EX == EX_MFMA64) {
         double a[PassRegs<P>::RT][PassRegs<P>::KC];
-        if constexpr (AB::on && P::AV)
+        if constexpr (AB::on && AB::template direct<P>())
             ab.template view<P>(a);
         else
             load_a<P>(stab, a, lane);
@@ -155,7 +155,7 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
     } else {
         constexpr bool BF = EX == EX_MFMA16B;
         typename Mfma16<BF>::V a[PassRegs16<P>::RB][PassRegs16<P>::KC];
-        if constexpr (AB::on && AB::template leading<P>())
+        if constexpr (AB::on && AB::template direct<P>())
             ab.template view<P>(a);
         else
             load_a16<P, BF>(stab, a, lane);
@@ -176,7 +176,7 @@ constexpr bool ablocks_on()
 }
 // the pass to run: its wide form when it takes its tiles from a block it does not start on
 template <class AB, class P, class PW>
-using WideIf = typename std::conditional<AB::wide_ok && !P::AV, PW, P>::type;
+using WideIf = typename std::conditional<AB::wide_ok && !AB::template direct<P>(), PW, P>::type;
 // the block type of an executor: FP64 tiles, 16-bit tiles (always small), or none (VALU)
 template <int D, int Q, int OPS, int EX, bool ON>
 using ABlocksFor = typename std::conditional<
