@@ -449,7 +449,7 @@ __global__ __launch_bounds__(256) void k_dstep(int64_t npts, const T *__restrict
 //   forward passes | wait, D-step | issue D(g+1) | transposed passes and scatter.
 // So the D stream of the next group overlaps the transposed passes and the forward
 // passes, and the gathers overlap the forward passes, without holding registers.
-constexpr int kDmaMinD = 6;                // orders p >= 5 (measured faster there; p <= 4 keeps the register kernel)
+constexpr int kDmaMinD = 6;                // orders p >= 5 (measured faster there; diffusion at p <= 4 keeps the register kernel)
 constexpr int kDmaLdsBudget = 53 * 1024;   // LDS bytes per workgroup of the DMA kernel
 
 __device__ __forceinline__ uint32_t lds_byte_addr(const void *p)
@@ -481,7 +481,9 @@ struct DmaShape {
     static constexpr int SLACK = 16 * cmax(B::DP, B::QP);
     static constexpr int FIXED = TB * 2 * SLACK + (int)sizeof(DevTables);
     static constexpr int E = cclamp((kDmaLdsBudget - FIXED) / PER, 1, 32);
-    static constexpr bool ok = D >= kDmaMinD;
+    // the mass operator from p = 4 (0.565 -> 0.529 ms at 78^3; at p = 2 the register
+    // kernel stays faster, 0.94 against 0.99 ms)
+    static constexpr bool ok = D >= kDmaMinD || (OPS == 1 && D >= 5);
     // one element per group at p = 8: eight waves share it (each pass has 6-7 column tiles)
     static constexpr int NT = (E == 1 && D >= 9) ? 512 : kThreads;
 };
