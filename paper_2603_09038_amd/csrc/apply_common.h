@@ -183,7 +183,7 @@ __device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassReg
 // for the whole kernel; at larger p they would not fit beside the rest, so F is read from
 // the LDS tables at the start of each group's forward passes and T at the start of its
 // transposed ones.  Either way the tables are read once per group and wave instead of once
-// per pass: at p = 6 that removes about 60 % of the kernel's LDS instructions.  Lane l
+// per pass: at p = 6 that removes about 40 % of the kernel's LDS instructions (counters).  Lane l
 // holds A[4 rt + (l & 3)][4 kc + (l >> 4)] as in load_a, so the results are those of the
 // per-pass loads.
 template <int D, int Q, bool ON>
