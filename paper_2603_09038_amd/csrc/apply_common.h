@@ -177,15 +177,16 @@ __device__ __forceinline__ void load_a(const DevTables *tab, double (&a)[PassReg
 // are whole 4x4 tiles of one of two blocks
 //   F = [B; G]      rows o < Q: B[o][k], Q <= o < 2Q: G[o-Q][k]; k < D (forward passes),
 //   T = [B^T G^T]   rows o < D; k < Q: B[k][o], Q <= k < 2Q: G[k-Q][o] (transposed passes)
-// (pass row tile rt is block tile amrt(rt), k chunk kc is amkc(kc); passes with AV false,
-// the G-only ones when Q is not a multiple of 4, read their tiles from the LDS tables as
-// before).  With Q a multiple of 4 (and at p <= 6 generally) both blocks stay in registers
-// for the whole kernel; at larger p they would not fit beside the rest, so F is read from
-// the LDS tables at the start of each group's forward passes and T at the start of its
+// (pass row tile rt is block tile amrt(rt), k chunk kc is amkc(kc)).  When Q is not a
+// multiple of 4 the G-only passes do not start on a tile; the kernels then run them as
+// wide passes on the whole block (DF3aW, DT1W), and only the mass term's third K-stacked
+// tensor (AV false) still reads its tiles from the LDS tables per pass.  Where both blocks
+// fit (p <= 6) they stay in registers for the whole kernel; at larger p F is read from the
+// LDS tables at the start of each group's forward passes and T at the start of its
 // transposed ones.  Either way the tables are read once per group and wave instead of once
-// per pass: at p = 6 that removes about 40 % of the kernel's LDS instructions (counters).  Lane l
-// holds A[4 rt + (l & 3)][4 kc + (l >> 4)] as in load_a, so the results are those of the
-// per-pass loads.
+// per pass: at p = 6 that removes about 40 % of the kernel's LDS instructions (counters).
+// Lane l holds A[4 rt + (l & 3)][4 kc + (l >> 4)] as in load_a, so the results are those
+// of the per-pass loads.
 template <int D, int Q, bool ON>
 struct ABlocks {
     static constexpr bool on = ON, wide_ok = ON;

@@ -168,19 +168,14 @@ __device__ __forceinline__ void run_pass(const T *in, int szin, const DevTables 
 // of a block when Q is not a multiple of 4 (dz forward, dx transposed) then run as wide
 // passes on the whole block, so no pass keeps tiles of its own beside the block (with per-
 // pass tiles beside it the p = 8 diffusion kernel needed 144 registers and lost a wave per
-// SIMD: 1.32 -> 1.48 ms).
-template <int D, int Q, int OPS>
-constexpr bool ablocks_on()
-{
-    return true;
-}
-// the pass to run: its wide form when it takes its tiles from a block it does not start on
+// SIMD: 1.32 -> 1.48 ms).  WideIf picks the pass to run: its wide form when it would take
+// its tiles from a block it does not start on.
 template <class AB, class P, class PW>
 using WideIf = typename std::conditional<AB::wide_ok && !AB::template direct<P>(), PW, P>::type;
 // the block type of an executor: FP64 tiles, 16-bit tiles (always small), or none (VALU)
 template <int D, int Q, int OPS, int EX, bool ON>
 using ABlocksFor = typename std::conditional<
-    EX == EX_MFMA64, ABlocks<D, Q, ON && ablocks_on<D, Q, OPS>()>,
+    EX == EX_MFMA64, ABlocks<D, Q, ON>,
     typename std::conditional<(EX >= EX_MFMA16F), ABlocks16<D, Q, EX == EX_MFMA16B, ON>,
                               ABlocks<D, Q, false>>::type>::type;
 
