@@ -21,25 +21,40 @@ namespace hexpa {
 
 namespace {
 
-constexpr int kDiagThreads = 512;
+constexpr int kDiagThreads = 256;
 
 // per-axis table index of each stored component (D order 00, 01, 02, 11, 12, 22, mass)
 enum : int { T_B2 = 0, T_BG = 1, T_G2 = 2 };
+
+// NR = NC Q^2 contiguous a-rows of D per element; a workgroup takes EPB consecutive
+// elements (one at high order, up to 16 at low order so that its threads have work).  The
+// first contraction reads D straight from HBM into registers (each thread one a-row), so
+// the only LDS arrays are the two intermediate tensors and the tables (about 31 KB at
+// Q = 8): several workgroups share a CU and their D streams overlap one another's
+// arithmetic.
+template <int D, int Q, int OPS>
+struct DiagShape {
+    static constexpr bool kMass = OPS & 1, kDiff = OPS & 2;
+    static constexpr int NC = kDiff ? (kMass ? 7 : 6) : 1;
+    static constexpr int NZ = kDiff ? 3 : 1;
+    static constexpr int NR = NC * Q * Q;
+    static constexpr int EPB = NR >= kDiagThreads ? 1 : (kDiagThreads / NR > 16 ? 16 : kDiagThreads / NR);
+};
 
 template <int D, int Q, int OPS>
 __global__ __launch_bounds__(kDiagThreads) void k_diag(int64_t nelem, const int32_t *__restrict__ emap,
                                                        const double *__restrict__ qd,
                                                        const DevTables *__restrict__ tab, double *__restrict__ diag)
 {
-    constexpr bool kMass = OPS & 1, kDiff = OPS & 2;
-    constexpr int NC = kDiff ? (kMass ? 7 : 6) : 1;
-    constexpr int NZ = kDiff ? 3 : 1;
+    using S = DiagShape<D, Q, OPS>;
+    constexpr bool kMass = S::kMass, kDiff = S::kDiff;
+    constexpr int NC = S::NC, NZ = S::NZ, NR = S::NR, EPB = S::EPB;
     constexpr int Q3 = Q * Q * Q, D3 = D * D * D, QD = Q * D;
+    constexpr int DP = D | 1;              // odd row pitch of U: the a-row writes spread over the banks
+    constexpr int SU = NR * DP, SV = NZ * Q * D * D;
     __shared__ double tb[3][QD];           // B^2, BG, G^2 as [a][i]
-    __shared__ double sq[NC * Q3];         // D of the element, [t][c][b][a]; then V
-    __shared__ double U[NC * Q * Q * D];   // [t][c][b][i]
-    static_assert(NZ * Q * D * D <= NC * Q3, "V reuses the storage of D");
-    double *V = sq;                        // [z][c][j][i], written once D is no longer read
+    __shared__ double U[EPB * SU];         // per element [t][c][b][i]
+    __shared__ double V[EPB * SV];         // per element [z][c][j][i]
     const int tid = threadIdx.x;
     for (int t = tid; t < QD; t += kDiagThreads) {
         const double b = tab->B[t], g = tab->G[t];
@@ -47,30 +62,37 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag(int64_t nelem, const int3
         tb[T_BG][t] = b * g;
         tb[T_G2][t] = g * g;
     }
-    const int64_t e = blockIdx.x;
-    const double *src = qd + e * (int64_t)(NC * Q3);
-    for (int t = tid; t < NC * Q3; t += kDiagThreads) sq[t] = src[t];
+    const int64_t e0 = (int64_t)blockIdx.x * EPB;
+    const int ne = (int)(nelem - e0 < EPB ? nelem - e0 : EPB);
+    const double *src = qd + e0 * (int64_t)(NC * Q3);  // the ne elements' rows are consecutive
     __syncthreads();
 
-    // axis a: U_t(i,b,c) = sum_a X_t[a][i] D_t(a,b,c)
-    for (int L = tid; L < NC * Q * Q * D; L += kDiagThreads) {
-        const int i = L % D, bc = (L / D) % (Q * Q), t = L / (D * Q * Q);
+    // axis a: U_t(i,b,c) = sum_a X_t[a][i] D_t(a,b,c); row (t,c,b) of D is contiguous in a
+    for (int R = tid; R < ne * NR; R += kDiagThreads) {
+        const int t = (R % NR) / (Q * Q);
+        double d[Q];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) d[a] = __builtin_nontemporal_load(src + (int64_t)R * Q + a);
         int xt = T_B2;  // D_11, D_12, D_22 and the mass term
         if (kDiff && t == 0) xt = T_G2;
         if (kDiff && (t == 1 || t == 2)) xt = T_BG;
         const double *X = tb[xt];
-        const double *Dt = sq + t * Q3 + bc * Q;
-        double acc = 0.0;
 #pragma unroll
-        for (int a = 0; a < Q; ++a) acc = fma(X[a * D + i], Dt[a], acc);
-        U[L] = acc;
+        for (int i = 0; i < D; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < Q; ++a) acc = fma(X[a * D + i], d[a], acc);
+            U[R * DP + i] = acc;
+        }
     }
     __syncthreads();
 
     // axis b: terms grouped by their third-axis table
-    for (int L = tid; L < NZ * Q * D * D; L += kDiagThreads) {
-        const int i = L % D, j = (L / D) % D, c = (L / (D * D)) % Q, z = L / (D * D * Q);
-        auto u = [&](int t, int b) { return U[((t * Q + c) * Q + b) * D + i]; };
+    for (int L = tid; L < ne * SV; L += kDiagThreads) {
+        const int le = L / SV, l = L - le * SV;
+        const int i = l % D, j = (l / D) % D, c = (l / (D * D)) % Q, z = l / (D * D * Q);
+        const double *Ue = U + le * SU;
+        auto u = [&](int t, int b) { return Ue[((t * Q + c) * Q + b) * DP + i]; };
         double acc = 0.0;
 #pragma unroll
         for (int b = 0; b < Q; ++b) {
@@ -94,33 +116,42 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag(int64_t nelem, const int3
     __syncthreads();
 
     // axis c, then the scatter-add through the DOF map
-    for (int I = tid; I < D3; I += kDiagThreads) {
+    for (int L = tid; L < ne * D3; L += kDiagThreads) {
+        const int le = L / D3, I = L - le * D3;
         const int i = I % D, j = (I / D) % D, k = I / (D * D);
+        const double *Ve = V + le * SV;
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < Q; ++c)
 #pragma unroll
-            for (int z = 0; z < NZ; ++z) acc = fma(tb[z][c * D + k], V[((z * Q + c) * D + j) * D + i], acc);
-        unsafeAtomicAdd(diag + emap[e * D3 + I], acc);
+            for (int z = 0; z < NZ; ++z) acc = fma(tb[z][c * D + k], Ve[((z * Q + c) * D + j) * D + i], acc);
+        unsafeAtomicAdd(diag + emap[e0 * D3 + L], acc);
     }
+}
+
+template <int D, int Q, int OPS>
+void launch_diag_k(const pa_op *op, double *diag, hipStream_t s)
+{
+    constexpr int EPB = DiagShape<D, Q, OPS>::EPB;
+    const int64_t ne = op->nelem;
+    const dim3 grid((unsigned)((ne + EPB - 1) / EPB)), block(kDiagThreads);
+    hipLaunchKernelGGL((k_diag<D, Q, OPS>), grid, block, 0, s, ne, op->d_elem_dofs, op->d_qdata, op->d_tab, diag);
+}
+
+template <int D, int Q>
+hipError_t launch_diag_q(const pa_op *op, double *diag, hipStream_t s)
+{
+    if (op->ops == 1) launch_diag_k<D, Q, 1>(op, diag, s);
+    if (op->ops == 2) launch_diag_k<D, Q, 2>(op, diag, s);
+    if (op->ops == 3) launch_diag_k<D, Q, 3>(op, diag, s);
+    return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_diag_p(const pa_op *op, double *diag, hipStream_t s)
 {
-    constexpr int D = P + 1;
-    const dim3 grid(op->nelem), block(kDiagThreads);
-    const int64_t ne = op->nelem;
-    if (op->q == P + 1) {
-        if (op->ops == 1) hipLaunchKernelGGL((k_diag<D, P + 1, 1>), grid, block, 0, s, ne, op->d_elem_dofs, op->d_qdata, op->d_tab, diag);
-        if (op->ops == 2) hipLaunchKernelGGL((k_diag<D, P + 1, 2>), grid, block, 0, s, ne, op->d_elem_dofs, op->d_qdata, op->d_tab, diag);
-        if (op->ops == 3) hipLaunchKernelGGL((k_diag<D, P + 1, 3>), grid, block, 0, s, ne, op->d_elem_dofs, op->d_qdata, op->d_tab, diag);
-    } else {
-        if (op->ops == 1) hipLaunchKernelGGL((k_diag<D, P + 2, 1>), grid, block, 0, s, ne, op->d_elem_dofs, op->d_qdata, op->d_tab, diag);
-        if (op->ops == 2) hipLaunchKernelGGL((k_diag<D, P + 2, 2>), grid, block, 0, s, ne, op->d_elem_dofs, op->d_qdata, op->d_tab, diag);
-        if (op->ops == 3) hipLaunchKernelGGL((k_diag<D, P + 2, 3>), grid, block, 0, s, ne, op->d_elem_dofs, op->d_qdata, op->d_tab, diag);
-    }
-    return hipGetLastError();
+    if (op->q == P + 1) return launch_diag_q<P + 1, P + 1>(op, diag, s);
+    return launch_diag_q<P + 1, P + 2>(op, diag, s);
 }
 
 }  // namespace
