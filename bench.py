@@ -120,6 +120,27 @@ def warm(fn, seconds, min_calls=1):
     return k
 
 
+def stream_read_gbps(nbytes=1 << 31, launches=10):
+    """Rate of a plain device-wide read on this machine: torch.sum over 2 GiB of FP64, timed
+    with HIP events.  Context for the roofline fraction (the practical ceiling of a streaming
+    kernel differs from machine to machine), never part of `value`."""
+    import torch
+    a = torch.rand(nbytes // 8, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        a.sum()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(launches):
+        a.sum()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    del a
+    torch.cuda.empty_cache()
+    return nbytes / (ms * 1e-3) / 1e9
+
+
 def time_kernel(op, hexpa, x, y, launches, warm_s=0.3):
     """Mean duration of the fused kernel alone (pa_apply_add: one launch), HIP events on the
     stream the kernel is launched on (torch's current stream, which the binding passes)."""
@@ -732,6 +753,9 @@ def main():
     log(f"timed {args.steps} steps: {ms_step:.4f} ms/step, {value:.2f} GDOF/s")
     dom = max(rows, key=lambda r: r["kernel_ms"])  # the kernel with the largest share of a step
     pd, qd = dom["p"], dom["q1d"]
+    stream = stream_read_gbps()
+    dom_gbs = dom["alg_bytes"] / (dom["kernel_ms"] * 1e-3) / 1e9
+    log(f"plain device-wide read on this machine: {stream:.0f} GB/s")
     out = {
         "metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -740,12 +764,13 @@ def main():
                                "perturbed hex meshes of the unit cube (about 30 M DOFs each), kappa=1, x~U[-1,1]; "
                                "one step = one apply at each order",
                    "orders": [r["p"] for r in rows], "ndof_per_step": total_dofs},
-        "roofline": {"bound": "hbm", "achieved": dom["alg_bytes"] / (dom["kernel_ms"] * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": dom_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["hbm_frac"],
                      "traffic": measured_traffic(f"k_apply_c3_p{pd}_diffusion_{dom['variant']}_hbm_traffic"),
                      "kernel": f"k_apply<D={pd + 1},Q={qd},diffusion,{dom['variant']}> (p={pd}, {dom['n']}^3)",
                      "alg_bytes_per_launch": dom["alg_bytes"], "alg_bytes_per_dof": dom["alg_bytes_per_dof"],
-                     "kernel_ms_mean": dom["kernel_ms"], "fp64_frac": dom["fp64_frac"]},
+                     "kernel_ms_mean": dom["kernel_ms"], "fp64_frac": dom["fp64_frac"],
+                     "stream_read_GBps": stream, "frac_of_stream_read": dom_gbs / stream},
         "sweep": rows,
     }
     if not args.no_mass:

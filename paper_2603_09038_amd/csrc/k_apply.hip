@@ -77,15 +77,24 @@ __device__ __forceinline__ int qtpos(int r)
     return ch * Chan<Q, M>::CS + Chan<Q, M>::qpos(r - ch * Q * Q * Q);
 }
 
-// Workgroup size and LDS budget of the register-staged kernel: diffusion at p <= 4 runs
-// two-wave workgroups with a 24 KB element budget (two elements at p = 4; fewer waves wait
-// at each barrier, more workgroups per CU); everything else four waves and a 48 KB budget
-// (measured per order).
-template <int D, int OPS, int EX>
+// Workgroup size, LDS budget and register budget (waves per SIMD) of the register-staged
+// kernel, measured per order.  Diffusion at p <= 4 runs two-wave workgroups (fewer waves
+// wait at each barrier, more workgroups per CU): a 24 KB element budget at p = 4 (two
+// elements), 16 KB at p <= 2 with at least six waves per SIMD (p = 2: 2.59 -> 2.49 ms at
+// 155^3; the smaller groups put seven workgroups on a CU instead of five).  The mass
+// operator at p <= 2 with Q = p + 2 keeps four waves but a 20 KB budget and six waves per
+// SIMD (p = 2: 0.94 -> 0.74 ms: a group's arithmetic is small against its D, map and x
+// traffic, so what hides the memory latency is the number of groups in flight per CU, six,
+// not three; at p = 3, at Q = p + 1 and in the matrix-free stage that register budget
+// would spill).  Everything else: four waves, 48 KB, three waves per SIMD.
+template <int D, int Q, int OPS, int EX, int STAGE = 0>
 struct ApplyCfg {
     static constexpr bool SMALL = (OPS & 2) != 0 && D <= 5 && (EX == 0 || EX == 1);
+    static constexpr bool DIFF_LO = SMALL && D <= 3 && STAGE == 0;
+    static constexpr bool MASS_LO = OPS == 1 && D <= 3 && Q == D + 1 && (EX == 0 || EX == 1) && STAGE == 0;
     static constexpr int NT = SMALL ? 128 : kThreads;
-    static constexpr int BUDGET = SMALL ? 24 * 1024 : kLdsBudget;
+    static constexpr int BUDGET = DIFF_LO ? 16 * 1024 : SMALL ? 24 * 1024 : MASS_LO ? 20 * 1024 : kLdsBudget;
+    static constexpr int MINW = DIFF_LO || MASS_LO ? 6 : kMinWavesPerEU;
 };
 
 // D of one group into registers: slot s of thread tid is qp entry L = tid + s*THREADS.
@@ -187,7 +196,7 @@ using ABlocksFor = typename std::conditional<
 // no stored D; the D-step recomputes it at every quadrature point from the element's eight
 // vertices (staged in LDS per group) and the coefficient, with the setup kernel's code.
 template <int D, int Q, int OPS, int EX, bool ATOMIC, int STAGE = 0>
-__global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_apply(
+__global__ __launch_bounds__((ApplyCfg<D, Q, OPS, EX, STAGE>::NT), (ApplyCfg<D, Q, OPS, EX, STAGE>::MINW)) void k_apply(
     int nelem, int ngroups, const int32_t *__restrict__ elist, const int32_t *__restrict__ emap,
     const typename ExT<EX>::T *__restrict__ qd, const DevTables *__restrict__ tab,
     const typename ExT<EX>::T *__restrict__ x, typename ExT<EX>::T *__restrict__ y,
@@ -195,7 +204,7 @@ __global__ __launch_bounds__((ApplyCfg<D, OPS, EX>::NT), kMinWavesPerEU) void k_
     CoeffDev cf)
 {
     using T = typename ExT<EX>::T;
-    using CFG = ApplyCfg<D, OPS, EX>;
+    using CFG = ApplyCfg<D, Q, OPS, EX, STAGE>;
     using S = Shape<D, Q, OPS, (int)sizeof(T), CFG::NT, CFG::BUDGET>;
     constexpr int NT = S::THREADS;
     constexpr int E = S::E, D3 = S::D3, Q3 = S::Q3, NS = S::NS, NC = S::NCOMP, NM = GroupRegs<S>::NM;
@@ -475,17 +484,21 @@ struct DmaShape {
     // footprint keeps four workgroups per CU for the 16-bit apply at p = 6)
     static constexpr int SLACK = 16 * cmax(B::DP, B::QP);
     static constexpr int FIXED = TB * 2 * SLACK + (int)sizeof(DevTables);
-    static constexpr int E = cclamp((kDmaLdsBudget - FIXED) / PER, 1, 32);
+    // the mass operator: a 40 KB budget and four waves per SIMD, so four workgroups share
+    // a CU instead of three (p = 4: 0.529 -> 0.485 ms at 78^3, p = 6: 0.481 -> 0.470 ms)
+    static constexpr int BUDGET = OPS == 1 ? 40 * 1024 : kDmaLdsBudget;
+    static constexpr int E = cclamp((BUDGET - FIXED) / PER, 1, 32);
     // the mass operator from p = 4 (0.565 -> 0.529 ms at 78^3; at p = 2 the register
     // kernel stays faster, 0.94 against 0.99 ms)
     static constexpr bool ok = D >= kDmaMinD || (OPS == 1 && D >= 5);
     // one element per group at p = 8: eight waves share it (each pass has 6-7 column tiles)
     static constexpr int NT = (E == 1 && D >= 9) ? 512 : kThreads;
+    static constexpr int MINW = NT == 512 ? 2 : OPS == 1 ? 4 : kMinWavesPerEU;
 };
 
 template <int D, int Q, int OPS, int EX, bool ATOMIC>
 __global__ __launch_bounds__((DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT),
-                             (DmaShape<D, Q, OPS, typename ExT<EX>::T>::NT == 512 ? 2 : kMinWavesPerEU)) void k_apply_dma(
+                             (DmaShape<D, Q, OPS, typename ExT<EX>::T>::MINW)) void k_apply_dma(
     int nelem, int ngroups, const int32_t *__restrict__ elist, const int32_t *__restrict__ emap,
     const typename ExT<EX>::T *__restrict__ qd, const DevTables *__restrict__ tab,
     const typename ExT<EX>::T *__restrict__ x, typename ExT<EX>::T *__restrict__ y)
@@ -707,7 +720,7 @@ static int capped(const pa_op *op, int nblocks)
 template <int D, int Q, int OPS, int EX>
 static hipError_t launch_unfused(const pa_op *op, const double *x, double *y, double *qbuf, hipStream_t s)
 {
-    using CFG = ApplyCfg<D, OPS, EX>;
+    using CFG = ApplyCfg<D, Q, OPS, EX, 1>;
     using S = Shape<D, Q, OPS, 8, CFG::NT, CFG::BUDGET>;
     const int n = op->nelem;
     const int ngroups = (n + S::E - 1) / S::E;
@@ -731,7 +744,7 @@ static hipError_t launch_unfused(const pa_op *op, const double *x, double *y, do
 template <int D, int Q, int OPS, int EX>
 static hipError_t launch_mf(const pa_op *op, const double *x, double *y, hipStream_t s)
 {
-    using CFG = ApplyCfg<D, OPS, EX>;
+    using CFG = ApplyCfg<D, Q, OPS, EX, 3>;
     using S = Shape<D, Q, OPS, 8, CFG::NT, CFG::BUDGET>;
     const int n = op->nelem;
     const int ngroups = (n + S::E - 1) / S::E;
@@ -748,7 +761,7 @@ static hipError_t launch_k(const pa_op *op, const typename ExT<EX>::T *qd, const
                            typename ExT<EX>::T *y, const int32_t *elist, int n, hipStream_t s)
 {
     using T = typename ExT<EX>::T;
-    using CFG = ApplyCfg<D, OPS, EX>;
+    using CFG = ApplyCfg<D, Q, OPS, EX>;
     constexpr bool DMA = DmaShape<D, Q, OPS, T>::ok;
     // elements per group and workgroup size exactly as the chosen kernel computes them
     constexpr int EG = DMA ? DmaShape<D, Q, OPS, T>::E : Shape<D, Q, OPS, (int)sizeof(T), CFG::NT, CFG::BUDGET>::E;
@@ -841,7 +854,7 @@ template <int D, int Q, int OPS, int EX, bool FUSED_STORED>
 static void group_shape(int *elems, int *threads)
 {
     using T = typename ExT<EX>::T;
-    using CFG = ApplyCfg<D, OPS, EX>;
+    using CFG = ApplyCfg<D, Q, OPS, EX, FUSED_STORED ? 0 : 1>;
     constexpr bool DMA = FUSED_STORED && DmaShape<D, Q, OPS, T>::ok;
     *elems = DMA ? DmaShape<D, Q, OPS, T>::E : Shape<D, Q, OPS, (int)sizeof(T), CFG::NT, CFG::BUDGET>::E;
     *threads = DMA ? DmaShape<D, Q, OPS, T>::NT : CFG::NT;
