@@ -485,15 +485,19 @@ struct DmaShape {
     static constexpr int SLACK = 16 * cmax(B::DP, B::QP);
     static constexpr int FIXED = TB * 2 * SLACK + (int)sizeof(DevTables);
     // the mass operator: a 40 KB budget and four waves per SIMD, so four workgroups share
-    // a CU instead of three (p = 4: 0.529 -> 0.485 ms at 78^3, p = 6: 0.481 -> 0.470 ms)
-    static constexpr int BUDGET = OPS == 1 ? 40 * 1024 : kDmaLdsBudget;
+    // a CU instead of three (p = 4: 0.529 -> 0.485 ms at 78^3, p = 6: 0.481 -> 0.470 ms);
+    // the 16-bit diffusion apply at p = 6: one element per group and five waves per SIMD,
+    // five workgroups per CU instead of four (Q = 8: 0.194 -> 0.182 ms at 32^3; at p = 5
+    // and 7 that register budget would spill)
+    static constexpr bool LP = TB == 4 && OPS == 2 && D == 7;
+    static constexpr int BUDGET = OPS == 1 ? 40 * 1024 : LP ? 26 * 1024 : kDmaLdsBudget;
     static constexpr int E = cclamp((BUDGET - FIXED) / PER, 1, 32);
     // the mass operator from p = 4 (0.565 -> 0.529 ms at 78^3; at p = 2 the register
     // kernel stays faster, 0.94 against 0.99 ms)
     static constexpr bool ok = D >= kDmaMinD || (OPS == 1 && D >= 5);
     // one element per group at p = 8: eight waves share it (each pass has 6-7 column tiles)
     static constexpr int NT = (E == 1 && D >= 9) ? 512 : kThreads;
-    static constexpr int MINW = NT == 512 ? 2 : OPS == 1 ? 4 : kMinWavesPerEU;
+    static constexpr int MINW = NT == 512 ? 2 : OPS == 1 ? 4 : LP ? 5 : kMinWavesPerEU;
 };
 
 template <int D, int Q, int OPS, int EX, bool ATOMIC>
