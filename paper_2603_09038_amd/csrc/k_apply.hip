@@ -480,8 +480,8 @@ struct DmaShape {
     using B = Shape<D, Q, OPS, (int)sizeof(T)>;
     static constexpr int TB = (int)sizeof(T);
     static constexpr int PER = TB * (B::SZ_A + B::SZ_B) + 12 * B::D3 + (TB == 8 ? 8 : 4) * B::D3;
-    // buffer tails for the padding columns of 16-column tiles (the exact bound; the smaller
-    // footprint keeps four workgroups per CU for the 16-bit apply at p = 6)
+    // buffer tails for the padding columns of 16-column tiles (the exact bound: a smaller
+    // footprint leaves room for more workgroups per CU)
     static constexpr int SLACK = 16 * cmax(B::DP, B::QP);
     static constexpr int FIXED = TB * 2 * SLACK + (int)sizeof(DevTables);
     // the mass operator: a 40 KB budget and four waves per SIMD, so four workgroups share
@@ -493,7 +493,8 @@ struct DmaShape {
     static constexpr int BUDGET = OPS == 1 ? 40 * 1024 : LP ? 26 * 1024 : kDmaLdsBudget;
     static constexpr int E = cclamp((BUDGET - FIXED) / PER, 1, 32);
     // the mass operator from p = 4 (0.565 -> 0.529 ms at 78^3; at p = 2 the register
-    // kernel stays faster, 0.94 against 0.99 ms)
+    // kernel stays faster: 0.94 against 0.99 ms before either had its occupancy setting,
+    // 0.75 ms now)
     static constexpr bool ok = D >= kDmaMinD || (OPS == 1 && D >= 5);
     // one element per group at p = 8: eight waves share it (each pass has 6-7 column tiles)
     static constexpr int NT = (E == 1 && D >= 9) ? 512 : kThreads;
