@@ -172,13 +172,36 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(int64_t nelem, const float *
     }
 }
 
-// grad[w] += sum over rows of partial[row][w], rows in a fixed order (FP64 accumulation).
-__global__ void k_reduce_rows(const float *__restrict__ partial, int rows, int nt, float *__restrict__ grad)
+// grad[w] += sum over rows of partial[row][w] in two passes, each in a fixed order (FP64
+// accumulation, so the result is reproducible): the rows are cut into kReduceChunks chunks;
+// a workgroup takes 64 columns of one chunk, its four waves summing every fourth row of it
+// and their four sums added in wave order (part2[chunk][w], FP64); then one thread per
+// column adds the chunks in order.  (One thread per column over all rows left most of the
+// GPU idle: a layer has 433-6928 weights, so 2-28 workgroups.)
+constexpr int kReduceChunks = 64;
+
+__global__ __launch_bounds__(256) void k_reduce_chunks(const float *__restrict__ partial, int rows, int nt,
+                                                       double *__restrict__ part2)
+{
+    __shared__ double red[4][64];
+    const int l = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int w = blockIdx.x * 64 + l, chunk = blockIdx.y;
+    const int r0 = (int)((int64_t)rows * chunk / kReduceChunks);
+    const int r1 = (int)((int64_t)rows * (chunk + 1) / kReduceChunks);
+    double a = 0.0;
+    if (w < nt)
+        for (int g = r0 + sl; g < r1; g += 4) a += partial[(int64_t)g * nt + w];
+    red[sl][l] = a;
+    __syncthreads();
+    if (sl == 0 && w < nt) part2[(int64_t)chunk * nt + w] = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
+}
+
+__global__ void k_reduce_rows(const double *__restrict__ part2, int nt, float *__restrict__ grad)
 {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nt) return;
     double a = 0.0;
-    for (int g = 0; g < rows; ++g) a += partial[(int64_t)g * nt + w];
+    for (int c = 0; c < kReduceChunks; ++c) a += part2[(int64_t)c * nt + w];
     grad[w] += (float)a;
 }
 
@@ -765,14 +788,28 @@ hipError_t forward_t(int64_t nelem, const float *params, float *wt, const float 
     return hipGetLastError();
 }
 
+// floats of the largest block of partial rows (even, so the FP64 chunk sums behind it are
+// 8-byte aligned)
+inline int64_t partial_rows_floats()
+{
+    using L1 = WgradShape<kNetCin, kNetCh>;
+    using L2 = WgradShape<kNetCh, kNetCh>;
+    using L3 = WgradShape<kNetCh, 1>;
+    const int64_t n = (int64_t)kWgradBlocks * std::max({L1::SL * L1::NT, L2::SL * L2::NT, L3::SL * L3::NT});
+    return (n + 1) & ~(int64_t)1;
+}
+
 // grad_w holds the layer's weights followed by its biases: the order of a partial row.
 template <int N, int CIN, int COUT>
 void wgrad_layer(int64_t nelem, const float *in, const float *dout, float *partial, float *grad_w, hipStream_t s)
 {
     using S = WgradShape<CIN, COUT>;
     hipLaunchKernelGGL((k_conv_wgrad<N, CIN, COUT>), dim3(kWgradBlocks), dim3(256), 0, s, nelem, in, dout, partial);
-    hipLaunchKernelGGL(k_reduce_rows, dim3(nblk(S::NT)), dim3(256), 0, s, partial, kWgradBlocks * S::SL, S::NT,
-                       grad_w);
+    // the chunk sums go behind the largest partial-row block (nn_partial_floats)
+    double *part2 = reinterpret_cast<double *>(partial + partial_rows_floats());
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((S::NT + 63) / 64, kReduceChunks), dim3(256), 0, s, partial,
+                       kWgradBlocks * S::SL, S::NT, part2);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(nblk(S::NT)), dim3(256), 0, s, part2, S::NT, grad_w);
 }
 
 template <int N>
@@ -804,7 +841,8 @@ int64_t nn_partial_floats()
     using L1 = WgradShape<kNetCin, kNetCh>;
     using L2 = WgradShape<kNetCh, kNetCh>;
     using L3 = WgradShape<kNetCh, 1>;
-    return (int64_t)kWgradBlocks * std::max({L1::SL * L1::NT, L2::SL * L2::NT, L3::SL * L3::NT});
+    // partial rows, then the FP64 chunk sums (two floats each)
+    return partial_rows_floats() + 2 * (int64_t)kReduceChunks * std::max({L1::NT, L2::NT, L3::NT});
 }
 
 hipError_t nn_forward(int n, int64_t nelem, const float *params, float *wt, const float *x0, float *a1, float *a2,
