@@ -117,7 +117,7 @@ struct WgradShape {
     static constexpr int NT = COUT * CIN * 27 + COUT;
     static_assert(COUT % OB == 0 && NPAIR <= 256 && 256 % NPAIR == 0, "thread layout");
 };
-constexpr int kWgradBlocks = 256;
+constexpr int kWgradBlocks = 768;  // three workgroups per CU: the 16x16 layer's 162 registers allow three
 
 template <int N, int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_wgrad(int64_t nelem, const float *__restrict__ in,
