@@ -159,7 +159,8 @@ int pa_apply_constrained(pa_op *op, const double *x, double *y, void *stream);
 
 /* d = diag(A) (constrained = 0) or diag(A_c) (constrained != 0: 1 on essential rows),
    computed by sum factorization over the stored D (three one-index contractions with the
-   per-axis tables B^2, B G and G^2, one 512-thread workgroup per element).  Asynchronous. */
+   per-axis tables B^2, B G and G^2; 256-thread workgroups of one element at high order
+   and up to sixteen at low order).  Asynchronous. */
 int pa_diag(pa_op *op, double *d, int constrained, void *stream);
 
 /* Load vector b = G^T B^T (w det J f): f given at quadrature points, device
